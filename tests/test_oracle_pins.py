@@ -1,0 +1,376 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check is anchored on a
+published known-answer vector, a closed form derived independently (exact
+enumeration, transfer matrix, exact stationarity of the update operator),
+a limit, or an invariant of the dynamics.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import chain, exact, tables
+import qsg_workloads as W
+
+U32 = 2 ** 32
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 (paper Sec. 2.1.1 uses D.E. Shaw's philox_4x32_10)
+# --------------------------------------------------------------------------
+def test_philox_known_answers(philox_kat):
+    for ctr, key, want in philox_kat:
+        got = chain.philox(ctr, key)
+        assert [int(x) for x in got] == want
+
+
+def test_metropolis_r_is_uniform_32bit():
+    """Lane numbers assembled from bit-sliced levels are uniform 32-bit
+    integers: acceptance frequency of r <= thr is (thr+1)/2^32."""
+    rs = np.concatenate([chain.metropolis_r(42, 7, s, t, g)
+                         for s in range(40) for t in range(5) for g in range(3)])
+    n = rs.size
+    for thr in (2 ** 31 - 1, 2 ** 30 - 1, 3 * 2 ** 30 - 1, 2 ** 28 - 1):
+        p = (thr + 1) / U32
+        f = np.mean(rs.astype(np.uint64) <= thr)
+        assert abs(f - p) < 5 * math.sqrt(p * (1 - p) / n)
+    # every bit position is fair
+    for b in range(32):
+        f = np.mean((rs >> b) & 1)
+        assert abs(f - 0.5) < 5 * math.sqrt(0.25 / n)
+
+
+# --------------------------------------------------------------------------
+# Threshold tables (paper Sec. 1: Gamma(k); App. B: daemon levels e^-4k..)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [0.125, 0.29, 0.32])
+def test_equal_coupling_collapse(k):
+    """With Gamma = -ln tanh(k)/(2k) (the paper's equal-coupling relation)
+    the time coupling equals k, so a flip's weight change depends only on
+    the total number of unsatisfied bonds n = n_s + n_t, and the only
+    non-trivial factors are the paper's three daemon levels e^-4k, e^-8k,
+    e^-12k (App. B)."""
+    L_tau = 64
+    beta = k * L_tau
+    G = tables.gamma_of_equal_coupling(k)
+    thr = tables.metropolis_thresholds(beta, L_tau, [G])[0]
+    by_total = {}
+    for ns in range(5):
+        for nt in range(3):
+            by_total.setdefault(ns + nt, set()).add(int(thr[ns, nt]))
+    for n, vals in by_total.items():
+        assert len(vals) == 1, (n, vals)
+    for n in range(3, 7):
+        assert by_total[n] == {U32 - 1}
+    # daemon level probabilities as stated in App. B, from Python's float
+    # exp: the threshold over 2^32 matches them to the table's quantum
+    for n, m in ((2, 1), (1, 2), (0, 3)):
+        (v,) = by_total[n]
+        assert abs((v + 1) / U32 - math.exp(-4 * k * m)) < 2.0 / U32
+
+
+def test_thresholds_monotone_and_saturated():
+    beta, L_tau = 8.0, 128
+    lad = W.geometric_ladder(2.0, 4.0, 8)
+    thr = tables.metropolis_thresholds(beta, L_tau, lad).astype(np.int64)
+    k = beta / L_tau
+    for g, G in enumerate(lad):
+        kp = -0.5 * math.log(math.tanh(beta * G / L_tau))
+        pairs = sorted(((4 * k * (2 - ns) + 4 * kp * (1 - nt), thr[g, ns, nt])
+                        for ns in range(5) for nt in range(3)))
+        # non-increasing threshold in the energy change
+        for (e0, t0), (e1, t1) in zip(pairs, pairs[1:]):
+            assert t1 <= t0
+        for e, t in pairs:
+            if e <= 0:
+                assert t == U32 - 1
+            else:
+                assert abs((t + 1) / U32 - math.exp(-e)) < 2.0 / U32
+    # smaller Gamma => stronger time coupling => fewer accepted breaks
+    assert np.all(thr[0, :, 0] <= thr[-1, :, 0])
+
+
+def test_swap_tables_closed_form_edges():
+    beta, L_tau = 16.0, 256
+    lad = np.array([2.0, 2.0, 2.5, 3.0])
+    eq, ln, tabs = tables.swap_tables(beta, L_tau, lad)
+    assert list(eq) == [1, 0, 0]
+    assert ln[0] == 0
+    for g in (1, 2):
+        t = tabs[g].astype(np.int64)
+        assert len(t) == ln[g] > 0
+        assert np.all(np.diff(t) <= 0) and t[-1] > 0
+        d = (-0.5 * math.log(math.tanh(beta * lad[g] / L_tau))
+             + 0.5 * math.log(math.tanh(beta * lad[g + 1] / L_tau)))
+        # the table ends where 2^32 e^{-4 m d} drops to at most 1
+        m_end = len(t) + 1
+        assert U32 * math.exp(-4 * m_end * d) <= 1.0 + 1e-6
+        assert U32 * math.exp(-4 * (m_end - 1) * d) > 1.0 - 1e-6
+    with pytest.raises(ValueError):
+        tables.swap_tables(beta, L_tau, [3.0, 2.0])
+
+
+# --------------------------------------------------------------------------
+# Exact references cross-check each other
+# --------------------------------------------------------------------------
+def _lane0_couplings(L, seed):
+    Jx, Jy = chain.couplings(L, [seed] * 64)
+    jx = 1 - 2 * exact.bits_of_lane(Jx, 0)
+    jy = 1 - 2 * exact.bits_of_lane(Jy, 0)
+    return Jx, Jy, jx, jy
+
+
+def test_enumeration_matches_transfer_matrix():
+    _, _, jx, jy = _lane0_couplings(2, 5)
+    k, kp = 0.25, 0.7
+    e = exact.exact_moments(2, 4, jx, jy, k, kp)
+    tm = exact.transfer_matrix_averages(jx, jy, 4, k, kp)
+    assert abs(e["Bsp"] - tm["Bsp"]) < 1e-10
+    assert abs(e["Bt"] - tm["Bt"]) < 1e-10
+
+
+def test_classical_limit_of_enumeration():
+    """Gamma -> 0: weights concentrate on tau-uniform configurations and
+    <Bsp>/L_tau tends to the classical 2D +-J energy at beta."""
+    _, _, jx, jy = _lane0_couplings(2, 9)
+    beta, L_tau = 1.0, 4
+    k = beta / L_tau
+    kp = -0.5 * math.log(math.tanh(beta * 1e-6 / L_tau))
+    e = exact.exact_moments(2, L_tau, jx, jy, k, kp)
+    s = exact.spins_from_index(np.arange(16), 4)
+    b, _ = exact.bond_sums(s, 2, 1, jx, jy)
+    w = np.exp(beta * b - (beta * b).max())
+    cl = float((w * b).sum() / w.sum())
+    assert abs(e["Bsp"] / L_tau - cl) < 1e-6
+    assert abs(e["Bt"] - 16) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# Exact stationarity of the oracle's colour passes
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("beta,G", [(1.0, 1.0), (2.0, 3.0), (1.0, 0.4)])
+def test_colour_pass_keeps_boltzmann_stationary(beta, G):
+    """On L=2, L_tau=4 (2^16 states), build each colour pass's exact Markov
+    operator from the oracle's own local classes and its table (acceptance
+    (thr+1)/2^32); the Boltzmann distribution must be stationary up to the
+    table quantisation (< 2^-32 per flip)."""
+    L, L_tau = 2, 4
+    Jx, Jy, jx, jy = _lane0_couplings(L, 3)
+    k = beta / L_tau
+    kp = -0.5 * math.log(math.tanh(beta * G / L_tau))
+    idx, Bsp, Bt = exact.enumerate_states(L, L_tau, jx, jy)
+    pi = exact.boltzmann(Bsp, Bt, k, kp)
+    V = L * L * L_tau
+    cfg = ((idx[:, None] >> np.arange(V)[None, :]) & 1).astype(np.uint64)
+    ns, nt = chain.site_classes(L, L_tau, Jx, Jy, cfg.reshape(-1))
+    thr = tables.metropolis_thresholds(beta, L_tau, [G])[0].astype(np.float64)
+    p = (thr[ns, nt] + 1.0) / U32
+    worst = 0.0
+    for colour in (0, 1):
+        out = exact.half_sweep_apply(pi, p, exact.colour_sites(L, L_tau, colour))
+        worst = max(worst, float(np.max(np.abs(out - pi))))
+    assert worst < 1e-8
+    # the check has teeth: counting satisfied instead of unsatisfied time
+    # bonds (a plausible index slip) breaks stationarity by far more
+    bad = thr[:, ::-1].copy()
+    pb = (bad[ns, nt] + 1.0) / U32
+    dev = np.max(np.abs(exact.half_sweep_apply(pi, pb, exact.colour_sites(L, L_tau, 0)) - pi))
+    assert dev > 1e-4
+
+
+# --------------------------------------------------------------------------
+# The chain itself: statistics against exact averages
+# --------------------------------------------------------------------------
+def _lane_means(og, n_sweeps, burn=200):
+    og.run(burn, 0)
+    acc_sp = np.zeros((og.N, 64))
+    acc_t = np.zeros((og.N, 64))
+    for _ in range(n_sweeps):
+        og.run(1, 0)
+        acc_sp += og.Bsp.reshape(og.N, 64)
+        acc_t += og.Bt.reshape(og.N, 64)
+    return acc_sp / n_sweeps, acc_t / n_sweeps
+
+
+def _check_mean(lane_means, exact_value, nsig=5.0):
+    m = lane_means.mean()
+    se = lane_means.std(ddof=1) / math.sqrt(lane_means.size)
+    assert abs(m - exact_value) < nsig * se + 1e-9, (m, exact_value, se)
+
+
+@pytest.mark.parametrize("G", [0.6, 1.0])
+def test_chain_trajectory_matches_exact_evolution_L2(G):
+    """L=2, L_tau=4: for every lane, the expected time average of Bsp and Bt
+    over the first T sweeps from that lane's initial state is computed
+    exactly by evolving the observables with the exact sweep operator
+    (2^16 states).  The chain's lane averages must agree within their
+    spread.  No ergodicity is assumed (Metropolis accepts dE <= 0 with
+    probability 1, and on this tiny lattice that leaves several closed
+    classes, so long-run averages depend on the start)."""
+    L, L_tau, beta, T = 2, 4, 1.0, 300
+    Jx, Jy, jx, jy = _lane0_couplings(L, 3)
+    idx, Bsp, Bt = exact.enumerate_states(L, L_tau, jx, jy)
+    V = L * L * L_tau
+    cfg = ((idx[:, None] >> np.arange(V)[None, :]) & 1).astype(np.uint64)
+    ns, nt = chain.site_classes(L, L_tau, Jx, Jy, cfg.reshape(-1))
+    thr = tables.metropolis_thresholds(beta, L_tau, [G])[0].astype(np.float64)
+    p = (thr[ns, nt] + 1.0) / U32
+    want_sp = exact.expected_time_average(Bsp, p, L, L_tau, T)
+    want_t = exact.expected_time_average(Bt, p, L, L_tau, T)
+    diffs_sp, diffs_t = [], []
+    for rep in range(4):
+        og = chain.OracleGroup(L, L_tau, beta, [G], rep, 42, [3] * 64)
+        words = og.spins.copy()
+        start = np.array([sum(int((int(words[s]) >> j) & 1) << s for s in range(V))
+                          for j in range(64)])
+        got_sp = np.zeros(64)
+        got_t = np.zeros(64)
+        for _ in range(T):
+            og.run(1, 0)
+            got_sp += og.Bsp
+            got_t += og.Bt
+        diffs_sp.append(got_sp / T - want_sp[start])
+        diffs_t.append(got_t / T - want_t[start])
+    for d in (np.concatenate(diffs_sp), np.concatenate(diffs_t)):
+        se = d.std(ddof=1) / math.sqrt(d.size)
+        assert abs(d.mean()) < 5 * se + 1e-9, (d.mean(), se)
+
+
+def test_chain_matches_transfer_matrix_Ltau32():
+    L, L_tau, beta, G = 2, 32, 4.0, 2.0
+    _, _, jx, jy = _lane0_couplings(L, 11)
+    og = chain.OracleGroup(L, L_tau, beta, [G], 0, 42, [11] * 64)
+    msp, mt = _lane_means(og, 2000)
+    k = beta / L_tau
+    kp = -0.5 * math.log(math.tanh(beta * G / L_tau))
+    tm = exact.transfer_matrix_averages(jx, jy, L_tau, k, kp)
+    _check_mean(msp[0], tm["Bsp"])
+    _check_mean(mt[0], tm["Bt"])
+
+
+def test_decoupled_slices_are_classical_2d_metropolis():
+    """kp -> 0 (large Gamma, every n_t class shares one threshold): the
+    slices decouple into independent classical 2D +-J chains at coupling
+    k.  On L=4 (2^16 states per slice) compare with exact enumeration."""
+    L, L_tau, beta, G = 4, 2, 0.8, 60.0
+    thr = tables.metropolis_thresholds(beta, L_tau, [G])[0]
+    assert np.all(thr[:, 0] == thr[:, 1]) and np.all(thr[:, 1] == thr[:, 2])
+    Jx, Jy, jx, jy = _lane0_couplings(L, 21)
+    og = chain.OracleGroup(L, L_tau, beta, [G], 0, 42, [21] * 64)
+    msp, _ = _lane_means(og, 3000)
+    k = beta / L_tau
+    s = exact.spins_from_index(np.arange(1 << 16), 16)
+    b, _ = exact.bond_sums(s, L, 1, jx, jy)
+    w = np.exp(k * b - (k * b).max())
+    per_slice = float((w * b).sum() / w.sum())
+    _check_mean(msp[0], L_tau * per_slice)
+
+
+def test_tau_uniform_state_freezes_as_gamma_goes_to_zero():
+    L, L_tau, beta, G = 4, 4, 1.0, 1e-6
+    thr = tables.metropolis_thresholds(beta, L_tau, [G])[0]
+    assert np.all(thr[:, 0] == 0)  # every break of two time bonds: r == 0 only
+    V = L * L * L_tau
+    rng = np.random.Generator(np.random.PCG64(0))
+    plane = rng.integers(0, 2 ** 63, size=L * L, dtype=np.uint64)
+    spins = np.tile(plane, L_tau)
+    og = chain.OracleGroup(L, L_tau, beta, [G], 0, 42, [5] * 64, spins=spins)
+    og.run(50, 0)
+    assert np.array_equal(og.spins, spins)
+    assert V == spins.size
+
+
+def test_invariants_under_pt():
+    for L, L_tau, ng, per_lane in ((4, 8, 3, False), (6, 4, 4, True), (2, 2, 2, False)):
+        grp = W.tiny_group(L, L_tau, 1.5, ng, 0.5, 2.5, per_lane=per_lane)
+        og = chain.OracleGroup.from_workload_group(grp)
+        og.run(60, 5)  # raises if tracked and recomputed sums ever differ
+        V = L * L * L_tau
+        assert np.all((og.Bt - V) % 4 == 0)
+        assert np.all(np.abs(og.Bsp) <= 2 * V)
+        Bsp, Bt, _ = og.recompute()
+        assert np.array_equal(Bsp.reshape(-1), og.Bsp)
+        assert np.array_equal(Bt.reshape(-1), og.Bt)
+        # walker labels stay a permutation of the slots in every lane
+        wk = og.walker.reshape(ng, 64)
+        assert np.all(np.sort(wk, axis=0) == np.arange(ng)[:, None])
+
+
+def test_equal_gammas_rotate_walkers():
+    """All Gammas equal: every exchange is accepted, so a sequential PT step
+    carries the walker of slot 0 to slot N-1 and moves every other walker
+    down one slot; a round trip then takes exactly N PT steps."""
+    N = 5
+    og = chain.OracleGroup(4, 4, 1.0, [1.3] * N, 0, 42, [1] * 64)
+    steps = 40
+    for p in range(steps):
+        before = og.walker.reshape(N, 64).copy()
+        og.pt_step()
+        after = og.walker.reshape(N, 64)
+        assert np.array_equal(after[N - 1], before[0])
+        assert np.array_equal(after[:N - 1], before[1:])
+    rows = og.swaplog_rows()
+    assert np.all(rows == np.uint64(0xFFFFFFFFFFFFFFFF))
+    cnt = og.rt_count.reshape(N, 64)
+    tot = og.rt_sum.reshape(N, 64)
+    assert cnt.sum() > 0
+    assert np.all(tot[cnt > 0] == N * cnt[cnt > 0])
+
+
+def test_swap_acceptance_frequency_matches_exchange_probability():
+    """Start two slots with known Bt and measure how often the first PT
+    step accepts: e^{(kp_0-kp_1) D} within binomial error."""
+    L, L_tau, beta = 4, 8, 2.0
+    lad = [1.0, 1.25]
+    V = L * L * L_tau
+    k_p = [-0.5 * math.log(math.tanh(beta * G / L_tau)) for G in lad]
+    d = k_p[0] - k_p[1]
+    # slot 0: all spins aligned (Bt = V); slot 1: site 0 alternates along
+    # tau in every lane (Bt = V - 2 L_tau), so D = Bt1 - Bt0 = -2 L_tau
+    s0 = np.zeros(V, dtype=np.uint64)
+    s1 = np.zeros((L_tau, L * L), dtype=np.uint64)
+    s1[1::2, 0] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    spins = np.concatenate([s0, s1.reshape(-1)])
+    D = -2 * L_tau
+    m = -D // 4
+    p_exact = math.exp(-4 * m * d)
+    accepted = 0
+    trials = 0
+    for rep in range(60):
+        og = chain.OracleGroup(L, L_tau, beta, lad, rep, 42, [1] * 64, spins=spins)
+        assert np.all(og.Bt.reshape(2, 64)[1] - og.Bt.reshape(2, 64)[0] == D)
+        og.pt_step()
+        mask = int(og.swaplog_rows()[0][0])
+        accepted += bin(mask).count("1")
+        trials += 64
+    f = accepted / trials
+    assert abs(f - p_exact) < 5 * math.sqrt(p_exact * (1 - p_exact) / trials)
+
+
+@pytest.mark.slow
+def test_pt_marginals_match_transfer_matrix():
+    """Three slots on L=2, L_tau=32: with exchanges the chain still samples
+    each slot's own Boltzmann distribution (exact per-slot averages from the
+    transfer matrix)."""
+    L, L_tau, beta = 2, 32, 4.0
+    lad = [1.2, 2.0, 3.2]
+    _, _, jx, jy = _lane0_couplings(L, 11)
+    og = chain.OracleGroup(L, L_tau, beta, lad, 0, 42, [11] * 64)
+    og.run(200, 2)
+    n = 1500
+    acc_t = np.zeros((3, 64))
+    acc_sp = np.zeros((3, 64))
+    for _ in range(n):
+        og.run(2, 2)
+        acc_t += og.Bt.reshape(3, 64)
+        acc_sp += og.Bsp.reshape(3, 64)
+    acc_t /= n
+    acc_sp /= n
+    k = beta / L_tau
+    for g, G in enumerate(lad):
+        kp = -0.5 * math.log(math.tanh(beta * G / L_tau))
+        tm = exact.transfer_matrix_averages(jx, jy, L_tau, k, kp)
+        _check_mean(acc_t[g], tm["Bt"])
+        _check_mean(acc_sp[g], tm["Bsp"])
+    assert og.acc.sum() > 0
