@@ -1,0 +1,177 @@
+"""Benchmark of the MCQSG Metropolis + parallel-tempering hot path on one GPU.
+
+Workload: 64 disorder samples (one group of 64 replicas each), L=16,
+L_tau=128, beta=8, 32 Gammas geometric in [2, 4], PT every 10 sweeps; seeded
+synthetic couplings and spins.  A step is one PT chunk over every sample:
+10 sweeps (red + blue pass each), the energy/overlap pass, the PT step and
+the exchange pass.
+
+Prints one JSON line.  value = picoseconds per spin-update of the batched
+path (one launch per pass over all samples, replayed as a HIP graph);
+plain_ps_per_spin_update is the same work launched per sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# int32 VALU lane-ops per second: 256 CUs x 64 lanes x 2.4 GHz
+PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
+OPS_PER_PHILOX_BLOCK = 80  # 10 rounds x (2 mul-lo + 2 mul-hi + 4 xor), 32-bit
+
+
+def required_blocks_per_word(lanes: int = 64) -> float:
+    """Expected Philox blocks the bit-sliced MSB-first comparison needs for a
+    word whose `lanes` lanes are all undecided: a lane is decided at each
+    level with probability 1/2 and a block carries two levels, so the count
+    is E[ceil(M/2)] with M the largest of `lanes` geometric(1/2) levels."""
+    return sum(1.0 - (1.0 - 4.0 ** (-(k - 1))) ** lanes for k in range(1, 17))
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--samples", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(groups are independent; sharding them needs no communication)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import qsg_workloads as W
+    from paper_2402_03920_amd import qsg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = W.c2_plain_large(n_samples=args.samples)
+    pe = wl.pt_every
+    upd_per_sweep = wl.spin_updates_per_sweep()
+    words_per_sweep = sum(g.words for g in wl.groups)
+
+    ens = qsg.Ensemble(wl.groups, pt_every=pe, swaplog_cap=64)
+    ens.init_spins()
+    stream = ens.stream
+    flags = qsg.QSG_BATCHED | qsg.QSG_GRAPH
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    ens.sweep(pe * args.warmup, flags)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} batched steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    sec = timed(lambda: ens.sweep(pe * args.steps, flags))
+    wall = time.perf_counter() - t0
+    ps_batched = sec / (pe * args.steps * upd_per_sweep) * 1e12
+
+    print(f"[bench] timing {args.plain_steps} plain steps", file=sys.stderr, flush=True)
+    sec_plain = timed(lambda: ens.sweep(pe * args.plain_steps, qsg.QSG_PLAIN))
+    ps_plain = sec_plain / (pe * args.plain_steps * upd_per_sweep) * 1e12
+
+    # dominant kernel: the batched colour pass; average launch duration from
+    # events around sweeps without PT (two pass launches + one tiny counter
+    # update per sweep), on the stream the kernels run on
+    n_k = 2 * pe
+    sec_k = timed(lambda: ens.sweep(n_k, qsg.QSG_BATCHED | qsg.QSG_NO_PT))
+    pass_s = sec_k / (2 * n_k)
+    words_per_pass = words_per_sweep / 2
+    blocks = required_blocks_per_word()
+    ops_per_pass = words_per_pass * blocks * OPS_PER_PHILOX_BLOCK
+    achieved = ops_per_pass / pass_s / 1e12
+    t, p = ens.counters()
+    energies = ens.energies()
+    ens.close()
+
+    result = {
+        "metric": "ps/spin-update (1 GPU) batched vs plain",
+        "value": round(ps_batched, 5),
+        "unit": "ps/spin-update",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec / args.steps * 1e3, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{len(wl.groups)} samples x 64 replicas, L=16, L_tau=128, beta=8, "
+                        f"32 Gammas geometric in [2,4], PT every {pe} sweeps",
+            "step": f"{pe} sweeps + energy pass + PT step + exchange pass, all samples",
+            "spin_updates_per_step": upd_per_sweep * pe,
+        },
+        "plain_ps_per_spin_update": round(ps_plain, 5),
+        "batched_speedup_vs_plain": round(ps_plain / ps_batched, 4),
+        "spin_updates_per_s": upd_per_sweep * pe * args.steps / sec,
+        "wall_s_timed_region": round(wall, 4),
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_half_sweep_batched",
+            "achieved": round(achieved, 4),
+            "peak": round(PEAK_INT32_TOPS, 4),
+            "unit": "Tops/s (int32 VALU lane-ops)",
+            "frac": round(achieved / PEAK_INT32_TOPS, 4),
+            "traffic": None,
+            "avg_launch_us": round(pass_s * 1e6, 3),
+            "algorithmic_ops_per_launch": ops_per_pass,
+            "model": f"{blocks:.4f} Philox blocks/word x {OPS_PER_PHILOX_BLOCK} ops x "
+                     f"{int(words_per_pass)} words/launch",
+            "hbm_GBps_algorithmic": round(words_per_pass * 12 / pass_s / 1e9, 2),
+        },
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps)
+    print(json.dumps(result), flush=True)
+    del energies
+
+
+def cpu_baseline(wl, n_sweeps):
+    """The oracle, as it is, on a bounded sample: one sample of the workload
+    for a few sweeps with the OpenMP slot split over the host's cores."""
+    from oracle import chain
+    cores = len(os.sched_getaffinity(0))
+    threads = min(cores, 32)
+    g = wl.groups[0]
+    og = chain.OracleGroup.from_workload_group(g, log_cap=8)
+    print(f"[bench] cpu baseline: oracle, 1 sample, {n_sweeps} sweeps, {threads} threads",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    og.run(n_sweeps, 0, threads=threads)
+    dt = time.perf_counter() - t0
+    upd = n_sweeps * g.spin_updates_per_sweep
+    return {"value": round(dt / upd * 1e12, 2), "unit": "ps/spin-update", "cores": threads,
+            "kind": "oracle",
+            "sample": f"1 of {len(wl.groups)} samples (L=16, L_tau=128, 32 Gammas), "
+                      f"{n_sweeps} sweeps, no PT; {upd:.3e} spin-updates in {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * qsg.h -- C ABI of the MI355X MCQSG hot path: Metropolis plus parallel
+ * tempering over the Trotter-Suzuki (2+1)-D lattice of the 2D +-J quantum
+ * Ising spin glass (paper: "The QISG suite", Sec. 1 Eqs. (1)-(3), Sec. 2.1).
+ *
+ * Model.  Spins S(x,y,tau) = +-1 on an L x L x L_tau prism, periodic in all
+ * three directions (Sec. 1).  Space bonds (x,y)-(x+1,y) and (x,y)-(x,y+1)
+ * carry J = +-1 and coupling k = beta/L_tau; time bonds (x,y,tau)-(x,y,tau+1)
+ * carry kp_g = -1/2 ln tanh(beta Gamma_g / L_tau) (two-coupling form; the
+ * paper's equal-coupling form, Sec. 1, is kp = k).  A configuration at slot
+ * g has weight exp(k Bsp + kp_g Bt), with Bsp the sum of J S S' over space
+ * bonds and Bt the sum of S S' over time bonds (Eq. (3) split in two).
+ *
+ * Packing.  A *group* is 64 independent bit-lanes that share L, L_tau,
+ * beta, the Gamma ladder and the Monte Carlo key.  Lane j of every word is
+ * one chain ("replica"); lanes may share one disorder sample or each carry
+ * their own (per-lane coupling seeds).  Spins of a group are uint64 words
+ * laid out [slot g][tau][y][x]; bit j is lane j; bit 1 <=> S = -1 (the bit
+ * convention of App. D).  Couplings are uint64 words Jx[y][x], Jy[y][x],
+ * bit 1 <=> J = -1.  Slot g always holds Gamma_g (ascending ladder).
+ *
+ * Update.  One sweep = red pass then blue pass, colour (x+y+tau) mod 2,
+ * red = 0 (checkerboard, Sec. 2.1).  A spin with n_s unsatisfied space bonds
+ * and n_t unsatisfied time bonds is flipped iff r <= thr[g][n_s][n_t] with
+ * thr = ceil(2^32 min(1, e^{-dE})) - 1 and dE = 4k(2-n_s) + 4kp_g(1-n_t);
+ * r is lane j's 32-bit Philox4x32-10 number (Sec. 2.1.1) for counter
+ * (site, sweep, g<<4 | q, group_id): block q gives bit-levels 2q and 2q+1,
+ * bit (31-b) of r is bit j of level b.  After every `pt_every`-th sweep a
+ * parallel-tempering step (Sec. 2.1, exchange probability
+ * min(1, e^{(kp_g - kp_{g+1}) (Bt[g+1]-Bt[g])})) visits pairs g = 0..N-2 in
+ * order, each lane independently, and moves accepted lanes' configurations
+ * between the two slots.  All decisions are integer comparisons, so results
+ * are bit-exact and do not depend on launch configuration.
+ *
+ * Conventions.
+ *  - Memory: the caller owns every device buffer.  qsg_create carves its
+ *    state out of one caller-allocated device workspace of
+ *    qsg_workspace_bytes() bytes, which must stay alive until qsg_destroy.
+ *    The library allocates no device memory (hipGraph objects aside).
+ *    Host buffers passed in are read before the call returns.
+ *  - Streams: work is enqueued on the caller's HIP stream.  qsg_measure,
+ *    qsg_get_* and qsg_sync synchronise that stream.
+ *  - Errors: functions return QSG_OK or a negative qsg_status and never
+ *    abort or throw.  Invalid arguments leave the context unchanged
+ *    (QSG_E_INVALID); qsg_last_error() describes the last failure.  A device
+ *    error marks the context failed; later calls return QSG_E_STATE.
+ *  - Threads: one context must not be used from two threads at once.
+ */
+#ifndef QSG_H
+#define QSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qsg_ctx qsg_ctx;
+typedef int32_t qsg_status;
+
+#define QSG_OK 0
+#define QSG_E_INVALID (-1)     /* bad argument; nothing changed          */
+#define QSG_E_UNSUPPORTED (-2) /* valid but outside what is built        */
+#define QSG_E_DEVICE (-3)      /* a HIP call failed                      */
+#define QSG_E_STATE (-4)       /* context failed earlier / wrong state   */
+#define QSG_E_BUFFER (-5)      /* caller buffer too small                */
+#define QSG_E_INTERRUPTED (-6) /* deadline reached between chunks        */
+
+#define QSG_MAX_GAMMA 64
+
+/* Description of one group (64 lanes). */
+typedef struct {
+    uint32_t L;              /* linear size, even, 2..256                     */
+    uint32_t L_tau;          /* imaginary-time slices, even, 2..65536         */
+    double beta;             /* inverse temperature, > 0; k = beta / L_tau    */
+    uint32_t n_gamma;        /* ladder points (slots), 1..64                  */
+    uint32_t group_id;       /* Philox counter word 3 of this group           */
+    uint64_t mc_seed;        /* Philox key (lo, hi) of spins, sweeps and PT   */
+    uint64_t j_seed[64];     /* Philox key of lane j's couplings              */
+    uint32_t swap_table_cap; /* max swap-table entries per pair (0 = 4096)    */
+    uint32_t reserved;       /* must be 0                                     */
+} qsg_group_desc;
+
+/* Run-wide settings. */
+typedef struct {
+    uint32_t pt_every;    /* PT step after sweep t if (t+1) % pt_every == 0; 0 = none */
+    uint32_t swaplog_cap; /* PT steps kept in the swap log ring (>= 1)        */
+} qsg_run_config;
+
+/* qsg_sweep flags */
+#define QSG_PLAIN 0u    /* one launch per group and pass (per-sample launches) */
+#define QSG_BATCHED 1u  /* one launch per pass over every group                */
+#define QSG_GRAPH 2u    /* with QSG_BATCHED: replay a captured HIP graph       */
+#define QSG_NO_PT 4u    /* skip the PT steps that fall due                     */
+
+/* qsg_measure selectors (one at a time) */
+#define QSG_M_ENERGY 1u    /* int32 [G][N][64][2]: (Bsp, Bt) recomputed now      */
+#define QSG_M_OVERLAP 2u   /* int64 [G][N][32]: sum_sites S^{2p} S^{2p+1}, now   */
+#define QSG_M_ACCEPT 3u    /* uint64 [G][N-1]: accepted exchanges, all lanes     */
+#define QSG_M_WALKERS 4u   /* uint8  [G][N][64]: walker label at (slot, lane)    */
+#define QSG_M_SWAPLOG 5u   /* uint64 [G][cap][N-1]: masks, row p % cap           */
+#define QSG_M_ROUNDTRIP 6u /* qsg_roundtrip [G][N][64] by (walker, lane)         */
+#define QSG_M_SUMS 7u      /* int64 [G][N][192]: per PT step sums of pre-exchange
+                              Bsp[64], Bt[64], q[32], q^2[32]                   */
+#define QSG_M_COUNTERS 8u  /* uint64 [2]: sweeps done, PT steps done            */
+
+typedef struct {
+    uint32_t state; /* 0 never at slot 0, 1 heading up, 2 heading down */
+    uint32_t t_last;/* PT time of the last visit to slot 0              */
+    uint32_t count; /* completed round trips 0 -> N-1 -> 0               */
+    uint32_t pad;
+    uint64_t sum;   /* sum of their durations, in PT steps               */
+} qsg_roundtrip;
+
+/* Bytes of device workspace needed for these groups. 0 on invalid input. */
+size_t qsg_workspace_bytes(const qsg_group_desc* groups, uint32_t n_groups,
+                           const qsg_run_config* cfg);
+
+/* Create a context over `d_workspace` (device pointer, 256-byte aligned,
+ * >= qsg_workspace_bytes) on HIP stream `hip_stream` (hipStream_t, may be
+ * NULL for the null stream).  Builds the couplings on the device from the
+ * lane seeds; the ladder is unset until qsg_set_gamma_ladder. */
+qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups,
+                      const qsg_run_config* cfg, void* d_workspace,
+                      size_t ws_bytes, void* hip_stream, qsg_ctx** out);
+
+/* Set group `group`'s ladder: n_gamma host doubles, > 0, non-decreasing.
+ * Builds the Metropolis and exchange thresholds in binary128 on the host
+ * and uploads them.  QSG_E_UNSUPPORTED if an exchange table would exceed
+ * swap_table_cap. */
+qsg_status qsg_set_gamma_ladder(qsg_ctx* ctx, uint32_t group, const double* gamma);
+
+/* Random initial spins (Philox counter (site, 0, 2<<24 | g, group_id)) for
+ * every group; resets sweep/PT counters, walkers, round trips, sums. */
+qsg_status qsg_init_spins(qsg_ctx* ctx);
+
+/* n_sweeps sweeps of every group, with the PT steps that fall due.
+ * With a deadline set, returns QSG_E_INTERRUPTED after the PT chunk during
+ * which it passed; the state is then consistent and can be resumed. */
+qsg_status qsg_sweep(qsg_ctx* ctx, uint32_t n_sweeps, uint32_t flags);
+
+/* One PT step now (outside the cadence), every group. */
+qsg_status qsg_pt_swap(qsg_ctx* ctx);
+
+/* Copy a measurement (see QSG_M_*) to host memory; synchronises. */
+qsg_status qsg_measure(qsg_ctx* ctx, uint32_t what, void* host_out, size_t bytes);
+
+/* Spins of one group, n_words = n_gamma * L_tau * L * L, layout above. */
+qsg_status qsg_get_spins(qsg_ctx* ctx, uint32_t group, uint64_t* host, size_t n_words);
+qsg_status qsg_set_spins(qsg_ctx* ctx, uint32_t group, const uint64_t* host, size_t n_words);
+
+/* Couplings of one group: host Jx[L*L], Jy[L*L]. */
+qsg_status qsg_get_couplings(qsg_ctx* ctx, uint32_t group, uint64_t* jx, uint64_t* jy);
+
+/* Full checkpoint (spins, counters, energies, walkers, round trips, sums,
+ * logs) to/from a host buffer of qsg_state_bytes(ctx) bytes.  No random
+ * state exists: the generator is counter-based (Sec. 2.1.1 footnote). */
+size_t qsg_state_bytes(const qsg_ctx* ctx);
+qsg_status qsg_get_state(qsg_ctx* ctx, void* host, size_t bytes);
+qsg_status qsg_set_state(qsg_ctx* ctx, const void* host, size_t bytes);
+
+/* Thresholds of one group as uploaded: thr[N][15] (index n_s*3+n_t),
+ * swap_equal[N-1], swap_len[N-1], swap_thr[N-1][swap_table_cap]. */
+qsg_status qsg_get_tables(qsg_ctx* ctx, uint32_t group, uint32_t* thr,
+                          uint8_t* swap_equal, uint32_t* swap_len, uint32_t* swap_thr);
+
+/* Host-only table builder (no device): same arithmetic as
+ * qsg_set_gamma_ladder.  swap_thr has room for (n_gamma-1)*cap entries. */
+qsg_status qsg_build_tables(double beta, uint32_t L_tau, uint32_t n_gamma,
+                            const double* gamma, uint32_t cap, uint32_t* thr,
+                            uint8_t* swap_equal, uint32_t* swap_len, uint32_t* swap_thr);
+
+/* Wall-clock deadline checked between PT chunks of qsg_sweep (0: due now,
+ * so the next qsg_sweep stops after its first chunk); < 0 clears it. */
+qsg_status qsg_set_deadline(qsg_ctx* ctx, double seconds_from_now);
+
+/* Synchronise the context's stream. */
+qsg_status qsg_sync(qsg_ctx* ctx);
+
+/* Message of the last failure of this context (or of creation if NULL). */
+const char* qsg_last_error(const qsg_ctx* ctx);
+
+/* Release host objects; the caller then frees the workspace. */
+void qsg_destroy(qsg_ctx* ctx);
+
+/* Philox4x32-10 on the device, for known-answer checks: for i < n, out[4i..]
+ * = Philox(ctr = in[6i..6i+3], key = in[6i+4..6i+5]).  Device pointers. */
+qsg_status qsg_philox(const uint32_t* d_in, uint32_t* d_out, uint32_t n, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSG_H */

@@ -41,7 +41,7 @@ def lib() -> C.CDLL:
         _lib.oracle_init_couplings.argtypes = [C.c_int, C.c_void_p, C.c_void_p,
                                                C.c_void_p]
         _lib.oracle_init_spins.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint32,
-                                           C.c_uint64, C.c_void_p]
+                                           C.c_uint64, C.c_uint32, C.c_void_p]
         _lib.oracle_site_classes.argtypes = [C.c_int, C.c_int, C.c_void_p,
                                              C.c_void_p, C.c_void_p, C.c_int64,
                                              C.c_int, C.c_void_p, C.c_void_p]
@@ -83,9 +83,9 @@ def couplings(L: int, j_seeds) -> tuple:
     return Jx, Jy
 
 
-def initial_spins(L, L_tau, N, group_id, seed) -> np.ndarray:
+def initial_spins(L, L_tau, N, group_id, seed, slot_base=0) -> np.ndarray:
     S = np.zeros(N * L_tau * L * L, dtype=np.uint64)
-    lib().oracle_init_spins(L, L_tau, N, group_id, seed, _p(S))
+    lib().oracle_init_spins(L, L_tau, N, group_id, seed, slot_base, _p(S))
     return S
 
 
@@ -112,7 +112,7 @@ class _State(C.Structure):
         ("rt_count", C.c_void_p), ("rt_sum", C.c_void_p), ("acc", C.c_void_p),
         ("swaplog", C.c_void_p), ("log_cap", C.c_uint64),
         ("sum_Bsp", C.c_void_p), ("sum_Bt", C.c_void_p), ("sum_q", C.c_void_p),
-        ("sum_q2", C.c_void_p), ("counters", C.c_void_p),
+        ("sum_q2", C.c_void_p), ("counters", C.c_void_p), ("slot_base", C.c_uint32),
     ]
 
 
@@ -124,7 +124,7 @@ class OracleGroup:
     """
 
     def __init__(self, L, L_tau, beta, gammas, group_id, mc_seed, j_seeds,
-                 log_cap=4096, thr=None, swap=None, spins=None):
+                 log_cap=4096, thr=None, swap=None, spins=None, slot_base=0):
         self.L, self.L_tau, self.beta = int(L), int(L_tau), float(beta)
         self.gammas = np.asarray(gammas, dtype=np.float64)
         self.N = len(self.gammas)
@@ -146,8 +146,9 @@ class OracleGroup:
             self.sw_len = np.zeros(1, np.uint32)
             self.sw_off = np.zeros(1, np.uint64)
         self.Jx, self.Jy = couplings(self.L, self.j_seeds)
+        self.slot_base = int(slot_base)
         self.spins = (initial_spins(self.L, self.L_tau, N, self.group_id,
-                                    self.mc_seed) if spins is None
+                                    self.mc_seed, self.slot_base) if spins is None
                       else np.ascontiguousarray(spins, dtype=np.uint64).copy())
         self.Bsp = np.zeros(N * 64, dtype=np.int32)
         self.Bt = np.zeros(N * 64, dtype=np.int32)
@@ -175,12 +176,19 @@ class OracleGroup:
             _p(self.Bsp), _p(self.Bt), _p(self.walker), _p(self.rt_state),
             _p(self.rt_tlast), _p(self.rt_count), _p(self.rt_sum), _p(self.acc),
             _p(self.swaplog), self.log_cap, _p(self.sum_Bsp), _p(self.sum_Bt),
-            _p(self.sum_q), _p(self.sum_q2), _p(self.counters))
+            _p(self.sum_q), _p(self.sum_q2), _p(self.counters), self.slot_base)
 
     @classmethod
     def from_workload_group(cls, grp, **kw):
         return cls(grp.L, grp.L_tau, grp.beta, grp.gammas, grp.group_id,
                    grp.mc_seed, grp.j_seeds, **kw)
+
+    @classmethod
+    def single_slot(cls, grp, g, **kw):
+        """Slot g of a group on its own (valid between PT steps, where the
+        slots of a group evolve independently)."""
+        return cls(grp.L, grp.L_tau, grp.beta, [grp.gammas[g]], grp.group_id,
+                   grp.mc_seed, grp.j_seeds, slot_base=g, **kw)
 
     # ------------------------------------------------------------------
     @property

@@ -122,13 +122,13 @@ void oracle_init_couplings(int L, const uint64_t j_seed[64], uint64_t *Jx,
 /* Initial spins: word(s, g) = o0 | o1<<32 of Philox with counter
  * (s, 0, (2<<24)|g, group_id), s = x + L*(y + L*tau). */
 void oracle_init_spins(int L, int Ltau, int N, uint32_t group_id, uint64_t seed,
-                       uint64_t *spins) {
+                       uint32_t slot_base, uint64_t *spins) {
     size_t V = (size_t)L * L * Ltau;
     for (int g = 0; g < N; ++g)
         for (size_t s = 0; s < V; ++s) {
             uint32_t o[4];
-            philox_u64seed((uint32_t)s, 0u, (2u << 24) | (uint32_t)g, group_id,
-                           seed, o);
+            philox_u64seed((uint32_t)s, 0u, (2u << 24) | ((uint32_t)g + slot_base),
+                           group_id, seed, o);
             spins[(size_t)g * V + s] = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
         }
 }
@@ -298,6 +298,10 @@ typedef struct {
     int64_t *sum_Bsp, *sum_Bt; /* [N][64] sums of pre-swap values per PT step */
     int64_t *sum_q, *sum_q2;   /* [N][32]                                   */
     uint64_t *counters;      /* [0] sweeps done t, [1] PT steps done p   */
+    uint32_t slot_base;      /* slot g of this state is slot g+slot_base of the
+                                full ladder (random-number counters only); lets a
+                                test follow a few slots of a large group between
+                                PT steps, where slots evolve independently     */
 } oracle_state;
 
 static void pt_step(oracle_state *st, int *failed) {
@@ -305,6 +309,12 @@ static void pt_step(oracle_state *st, int *failed) {
     const int N = st->N;
     const size_t V = (size_t)st->L * st->L * st->Ltau;
     const uint32_t p = (uint32_t)st->counters[1];
+    if (N < 2) {
+        /* one slot: no exchange partner and no distinct end slots, so the
+         * step only advances the PT clock */
+        st->counters[1] = p + 1;
+        return;
+    }
 
     /* Tracked sums must equal sums recomputed from the configuration. */
     for (int g = 0; g < N; ++g) {
@@ -406,7 +416,7 @@ static void colour_pass(oracle_state *st, int g, int colour, uint32_t t) {
                 size_t s = site(&a, x, y, tau);
                 uint32_t r[64];
                 oracle_metropolis_r(st->mc_seed, st->group_id, (uint32_t)s, t,
-                                    (uint32_t)g, r);
+                                    (uint32_t)g + st->slot_base, r);
                 /* Neighbours have the other colour, and flipping lane j
                  * only touches bit j of the centre, so one read serves all
                  * 64 lanes. */

@@ -1,0 +1,132 @@
+// Internal layout shared by the host API and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace qsg {
+
+// Per-(walker, lane) round-trip tracker; same layout as qsg_roundtrip.
+struct RoundTrip {
+    uint32_t state;
+    uint32_t t_last;
+    uint32_t count;
+    uint32_t pad;
+    uint64_t sum;
+};
+
+// Counters the energy pass accumulates per slot: unsatisfied space bonds and
+// time bonds per lane, differing lane pairs per pair.
+constexpr int kCntStride = 64 + 64 + 32;  // int32 per slot
+// Per-slot measurement sums: Bsp[64], Bt[64], q[32], q^2[32] as int64.
+constexpr int kSumStride = 192;
+// Thresholds per slot, padded.
+constexpr int kThrStride = 16;
+
+// Exact division by a fixed d for x < 2^31: q = mulhi(x, m) >> s, or
+// x >> s when m == 0 (d a power of two).
+struct Divisor {
+    uint32_t m, s;
+};
+
+inline Divisor make_divisor(uint32_t d) {
+    Divisor r{0, 0};
+    uint32_t a = 0;
+    while ((1ull << (a + 1)) <= d) ++a;  // a = floor(log2 d)
+    if ((1u << a) == d) {
+        r.s = a;
+    } else {
+        // d in (2^a, 2^(a+1)): m = ceil(2^(32+a)/d) < 2^32, exact for x < 2^31
+        r.m = (uint32_t)(((1ull << (32 + a)) + d - 1) / d);
+        r.s = a;
+    }
+    return r;
+}
+
+// Everything a kernel needs to know about one group.  Lives on the host
+// (plain launches pass it by value) and in a device array (batched
+// launches index it).
+struct GroupDev {
+    uint32_t L, Ltau, N, gid;
+    uint32_t key0, key1;  // Monte Carlo key (mc_seed lo, hi)
+    uint32_t V;           // words per slot = L*L*Ltau
+    uint32_t sw_cap;      // entries per exchange table
+    uint32_t log_cap;     // rows of the swap log
+    uint32_t pad0;
+    Divisor div_half_plane, div_half_row, div_plane, div_row;
+    uint64_t* spins;          // [N][Ltau][L][L]
+    uint64_t* Jx;             // [L*L]
+    uint64_t* Jy;             // [L*L]
+    const uint64_t* jseed;    // [64] coupling keys
+    uint32_t* thr;            // [N][16]; [15] = class regime of the slot
+    uint32_t* sw_thr;         // [N-1][sw_cap]
+    uint32_t* sw_len;         // [N-1]
+    uint32_t* sw_eq;          // [N-1]
+    int32_t* cnt;             // [N][kCntStride]
+    int32_t* E;               // [N][64][2] current (Bsp, Bt)
+    uint32_t* walker;         // [N][64]
+    RoundTrip* rt;            // [N walkers][64 lanes]
+    uint64_t* acc;            // [N-1]
+    uint64_t* swaplog;        // [log_cap][N-1]
+    int64_t* sums;            // [N][kSumStride]
+    uint64_t* lastmask;       // [N] masks of the latest PT step (+ any flag at [N-1])
+    int32_t* meas;            // [N][kCntStride] scratch for on-demand measurement
+};
+
+// Launchers (qsg_kernels.hip).  All enqueue on `s` and return the launch
+// status.  `ctr` is the device pair (sweeps done, PT steps done); sweep and
+// PT kernels use ctr[0] + t_add and ctr[1] + p_add as their indices.
+hipError_t launch_init_couplings(const GroupDev& g, hipStream_t s);
+hipError_t launch_init_spins(const GroupDev& g, hipStream_t s);
+hipError_t launch_init_state(const GroupDev& g, hipStream_t s);
+hipError_t launch_half_sweep(const GroupDev& g, uint32_t colour, const uint32_t* ctr,
+                             uint32_t t_add, hipStream_t s);
+hipError_t launch_energy(const GroupDev& g, int32_t* cnt, hipStream_t s);
+hipError_t launch_pt(const GroupDev& g, const uint32_t* ctr, uint32_t p_add, hipStream_t s);
+hipError_t launch_advance(uint32_t* ctr, uint32_t dt, uint32_t dp, hipStream_t s);
+hipError_t launch_swap_apply(const GroupDev& g, hipStream_t s);
+hipError_t launch_zero32(void* p, size_t n_words32, hipStream_t s);
+hipError_t launch_philox(const uint32_t* in, uint32_t* out, uint32_t n, hipStream_t s);
+
+// Batched: one launch per pass over all groups.  `prefix[i]` is the first
+// block of group i (prefix[n_groups] = total blocks); a block finds its
+// group by a uniform binary search.
+struct BatchPlan {
+    const GroupDev* groups;  // device array [n_groups]
+    const uint32_t* prefix;  // device array [n_groups + 1]
+    uint32_t n_groups;
+    uint32_t n_blocks;
+};
+hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,
+                                     uint32_t t_add, hipStream_t s);
+hipError_t launch_energy_batched(const BatchPlan& plan, hipStream_t s);
+hipError_t launch_pt_batched(const GroupDev* groups, uint32_t n_groups, const uint32_t* ctr,
+                             uint32_t p_add, hipStream_t s);
+hipError_t launch_swap_apply_batched(const BatchPlan& plan, hipStream_t s);
+
+// Blocks one group needs in each pass (host and device agree on these).
+__host__ __device__ inline uint32_t sweep_blocks_per_slot(uint32_t V);
+__host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V);
+__host__ __device__ inline uint32_t swap_blocks(uint32_t V);
+
+constexpr int kSweepBlock = 256;   // threads per block of a colour pass
+constexpr int kEnergyWords = 16;   // words per thread in the energy pass
+constexpr int kEnergyBlock = 256;
+constexpr int kSwapBlock = 256;
+
+}  // namespace qsg
+
+namespace qsg {
+__host__ __device__ inline uint32_t sweep_blocks_per_slot(uint32_t V) {
+    return (V / 2 + kSweepBlock - 1) / kSweepBlock;
+}
+__host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V) {
+    const uint32_t per_block = kEnergyBlock * kEnergyWords;
+    return (V + per_block - 1) / per_block;
+}
+__host__ __device__ inline uint32_t swap_blocks(uint32_t V) {
+    return (V + kSwapBlock - 1) / kSwapBlock;
+}
+}  // namespace qsg

@@ -1,0 +1,610 @@
+// HIP kernels (gfx950, wave64) of the MCQSG Metropolis + parallel-tempering
+// hot path.  Paper: Sec. 2.1 (multi-spin coding, checkerboard Metropolis,
+// precomputed acceptance factors, parallel tempering), Sec. 2.1.1 (counter-
+// based Philox4x32-10 random numbers tied to the lattice update).
+//
+// Multi-spin coding here packs 64 independent chains of one site into a
+// uint64 (bit j = lane j), so a thread updates 64 spins with bitwise logic:
+//   * unsatisfied bonds: u = s ^ neighbour ^ J (bit set <=> J S S' < 0);
+//   * per-lane counts n_s (4 space bonds) and n_t (2 time bonds) as
+//     bit-sliced adders, turned into 15 one-hot class masks;
+//   * acceptance r_j <= thr[class_j]: lane numbers are bit-sliced over 32
+//     levels (bit 31-b of r_j is bit j of level b), so all 64 comparisons run
+//     together, most significant level first, and stop as soon as every lane
+//     of the wave is decided.  One Philox block yields two levels.
+// Nothing here is a dense contraction, so there is no matrix-core work: the
+// pass is integer VALU work on data streamed from HBM.
+#include <hip/hip_runtime.h>
+
+#include "qsg_internal.h"
+
+namespace qsg {
+namespace {
+
+constexpr uint32_t kM0 = 0xD2511F53u;
+constexpr uint32_t kM1 = 0xCD9E8D57u;
+constexpr uint32_t kW0 = 0x9E3779B9u;
+constexpr uint32_t kW1 = 0xBB67AE85u;
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// and xors with the key, the key advanced by the Weyl constants.
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = c.x * kM0;
+        const uint32_t hi0 = __umulhi(c.x, kM0);
+        const uint32_t lo1 = c.z * kM1;
+        const uint32_t hi1 = __umulhi(c.z, kM1);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += kW0;
+        k1 += kW1;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint64_t lo_hi(uint32_t lo, uint32_t hi) {
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Division of x < 2^31 by a block-uniform d >= 1 with a precomputed
+// multiplier: q = mulhi(x, m) >> s (see make_divisor on the host).
+__device__ __forceinline__ uint32_t fast_div(uint32_t x, Divisor d) {
+    return d.m ? (__umulhi(x, d.m) >> d.s) : (x >> d.s);
+}
+
+// Classes (n_s, n_t) whose flip can raise the energy (dE > 0), for the three
+// orderings of the two couplings; every other class has dE <= 0 and is
+// always accepted.  Regime 0: kp > 2k, 1: k < kp <= 2k, 2: kp <= k.
+template <int R> struct Classes;
+template <> struct Classes<0> {
+    static constexpr int n = 7;
+    static constexpr int ns[7] = {0, 1, 2, 3, 4, 0, 1};
+    static constexpr int nt[7] = {0, 0, 0, 0, 0, 1, 1};
+};
+template <> struct Classes<1> {
+    static constexpr int n = 7;
+    static constexpr int ns[7] = {0, 1, 2, 3, 0, 1, 0};
+    static constexpr int nt[7] = {0, 0, 0, 0, 1, 1, 2};
+};
+template <> struct Classes<2> {
+    static constexpr int n = 7;
+    static constexpr int ns[7] = {0, 1, 2, 0, 1, 0, 1};
+    static constexpr int nt[7] = {0, 0, 0, 1, 1, 2, 2};
+};
+template <> struct Classes<3> {  // any table: all fifteen classes
+    static constexpr int n = 15;
+    static constexpr int ns[15] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 3, 4, 4, 4};
+    static constexpr int nt[15] = {0, 1, 2, 0, 1, 2, 0, 1, 2, 0, 1, 2, 0, 1, 2};
+};
+
+__device__ __forceinline__ uint64_t all_if(uint32_t v, uint32_t bit) {
+    return 0ull - (uint64_t)((v >> bit) & 1u);  // block-uniform 0 or ~0
+}
+
+// ---------------------------------------------------------------------------
+// One Metropolis update of the colour-c word number `idx` of slot g.
+// Colour-c words of a slot are numbered tau-plane by tau-plane, row by row:
+// idx = tau*(L*L/2) + y*(L/2) + xh, x = 2*xh + ((c + y + tau) & 1).
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void update_word(const GroupDev& G, uint32_t g, uint32_t colour,
+                                            uint32_t t, uint32_t idx) {
+    using C = Classes<R>;
+    const uint32_t L = G.L;
+    const uint32_t P = L * L;
+    const uint32_t half_plane = P >> 1;
+    const uint32_t half_row = L >> 1;
+    const uint32_t tau = fast_div(idx, G.div_half_plane);
+    const uint32_t rem = idx - tau * half_plane;
+    const uint32_t y = fast_div(rem, G.div_half_row);
+    const uint32_t x = 2 * (rem - y * half_row) + ((colour + y + tau) & 1u);
+
+    const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+    const uint32_t xm = (x == 0) ? L - 1 : x - 1;
+    const uint32_t yp = (y + 1 == L) ? 0 : y + 1;
+    const uint32_t ym = (y == 0) ? L - 1 : y - 1;
+    const uint32_t tp = (tau + 1 == G.Ltau) ? 0 : tau + 1;
+    const uint32_t tm = (tau == 0) ? G.Ltau - 1 : tau - 1;
+
+    uint64_t* __restrict__ S = G.spins + (size_t)g * G.V;
+    const uint32_t row = y * L;
+    const uint32_t plane = tau * P;
+    const uint32_t s = plane + row + x;  // flat site index = RNG counter word 0
+
+    const uint64_t w = S[s];
+    const uint64_t nxp = S[plane + row + xp];
+    const uint64_t nxm = S[plane + row + xm];
+    const uint64_t nyp = S[plane + yp * L + x];
+    const uint64_t nym = S[plane + ym * L + x];
+    const uint64_t ntp = S[tp * P + row + x];
+    const uint64_t ntm = S[tm * P + row + x];
+    const uint64_t jxp = G.Jx[row + x];
+    const uint64_t jxm = G.Jx[row + xm];  // the -x bond is the +x bond of x-1
+    const uint64_t jyp = G.Jy[row + x];
+    const uint64_t jym = G.Jy[ym * L + x];
+
+    // unsatisfied-bond planes and their bit-sliced counts
+    const uint64_t u1 = w ^ nxp ^ jxp, u2 = w ^ nxm ^ jxm;
+    const uint64_t u3 = w ^ nyp ^ jyp, u4 = w ^ nym ^ jym;
+    const uint64_t a0 = u1 ^ u2, a1 = u1 & u2;
+    const uint64_t b0 = u3 ^ u4, b1 = u3 & u4;
+    const uint64_t s0 = a0 ^ b0, c0 = a0 & b0;
+    const uint64_t s1 = a1 ^ b1 ^ c0;
+    const uint64_t s2 = (a1 & b1) | (c0 & (a1 ^ b1));
+    const uint64_t t1 = w ^ ntp, t2 = w ^ ntm;
+
+    uint64_t NS[5], NT[3];
+    NS[0] = ~(s2 | s1 | s0);
+    NS[1] = s0 & ~s1 & ~s2;
+    NS[2] = s1 & ~s0;
+    NS[3] = s1 & s0;
+    NS[4] = s2;
+    NT[0] = ~(t1 | t2);
+    NT[1] = t1 ^ t2;
+    NT[2] = t1 & t2;
+
+    // thresholds of this slot (uniform across the block)
+    const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
+    uint32_t th[C::n];
+    uint64_t M[C::n];
+    uint64_t live = 0;
+#pragma unroll
+    for (int i = 0; i < C::n; ++i) {
+        th[i] = thr[C::ns[i] * 3 + C::nt[i]];
+        M[i] = NS[C::ns[i]] & NT[C::nt[i]];
+        if (R == 3) M[i] &= ~all_if(th[i] == 0xFFFFFFFFu ? 1u : 0u, 0);
+        live |= M[i];
+    }
+    // lanes outside the listed classes have dE <= 0: accepted outright
+    uint64_t acc = ~live;
+    uint64_t und = live;
+
+    const uint4 ctr_base = make_uint4(s, t, g << 4, G.gid);
+#pragma unroll 1
+    for (uint32_t q = 0; q < 16; ++q) {
+        if (!__any(und != 0)) break;  // every lane of the wave is decided
+        const uint4 o = philox(make_uint4(ctr_base.x, ctr_base.y, ctr_base.z | q, ctr_base.w),
+                               G.key0, G.key1);
+        const uint64_t lev[2] = {lo_hi(o.x, o.y), lo_hi(o.z, o.w)};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t bit = 31u - (2u * q + (uint32_t)h);
+            uint64_t T = 0;
+#pragma unroll
+            for (int i = 0; i < C::n; ++i) T |= M[i] & all_if(th[i], bit);
+            const uint64_t W = lev[h];
+            acc |= und & T & ~W;  // r bit 0 where thr bit 1: r < thr
+            und &= ~(T ^ W);      // still equal so far
+        }
+    }
+    acc |= und;  // equal on all 32 bits: r == thr, accepted
+    if (acc) S[s] = w ^ acc;
+}
+
+__device__ __forceinline__ void update_word_any(const GroupDev& G, uint32_t g, uint32_t colour,
+                                                uint32_t t, uint32_t idx) {
+    switch (G.thr[g * kThrStride + 15]) {  // regime of slot g, set with the table
+        case 0: update_word<0>(G, g, colour, t, idx); break;
+        case 1: update_word<1>(G, g, colour, t, idx); break;
+        case 2: update_word<2>(G, g, colour, t, idx); break;
+        default: update_word<3>(G, g, colour, t, idx); break;
+    }
+}
+
+__global__ void __launch_bounds__(kSweepBlock)
+k_half_sweep(const GroupDev G, uint32_t colour, const uint32_t* __restrict__ ctr, uint32_t t_add) {
+    const uint32_t t = ctr[0] + t_add;
+    const uint32_t g = blockIdx.y;
+    const uint32_t idx = blockIdx.x * kSweepBlock + threadIdx.x;
+    if (idx < (G.V >> 1)) update_word_any(G, g, colour, t, idx);
+}
+
+__device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ prefix,
+                                               uint32_t n_groups, uint32_t b) {
+    uint32_t lo = 0, hi = n_groups;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kSweepBlock)
+k_half_sweep_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
+                     uint32_t n_groups, uint32_t colour, const uint32_t* __restrict__ ctr,
+                     uint32_t t_add) {
+    const uint32_t t = ctr[0] + t_add;
+    const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
+    const GroupDev G = groups[gi];
+    const uint32_t local = blockIdx.x - prefix[gi];
+    const uint32_t nb = sweep_blocks_per_slot(G.V);
+    const uint32_t g = local / nb;
+    const uint32_t idx = (local - g * nb) * kSweepBlock + threadIdx.x;
+    if (idx < (G.V >> 1)) update_word_any(G, g, colour, t, idx);
+}
+
+// ---------------------------------------------------------------------------
+// Energy / overlap pass: per slot and lane, the number of unsatisfied space
+// bonds and time bonds (each bond counted once, from its lower endpoint),
+// and per lane pair (2p, 2p+1) the number of sites where they differ.
+// Each thread adds its words into bit-sliced vertical counters; each wave
+// then turns counters into per-lane totals with ballots and adds them to
+// the slot's counters with integer atomics (order-independent, exact).
+// ---------------------------------------------------------------------------
+template <int NB>
+__device__ __forceinline__ void vadd(uint64_t (&C)[NB], uint64_t x) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const uint64_t carry = C[i] & x;
+        C[i] ^= x;
+        x = carry;
+    }
+}
+
+template <int NB>
+__device__ __forceinline__ uint32_t lane_total(const uint64_t (&C)[NB], uint32_t j) {
+    uint32_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+        tot += (uint32_t)__popcll(__ballot((int)((C[i] >> j) & 1u))) << i;
+    return tot;
+}
+
+__device__ __forceinline__ void energy_block(const GroupDev& G, uint32_t g, uint32_t blk,
+                                             int32_t* __restrict__ cnt) {
+    const uint32_t L = G.L, P = L * L, V = G.V;
+    const uint64_t* __restrict__ S = G.spins + (size_t)g * V;
+    uint64_t Csp[6] = {0, 0, 0, 0, 0, 0};  // <= 2*kEnergyWords = 32
+    uint64_t Ct[5] = {0, 0, 0, 0, 0};
+    uint64_t Cq[5] = {0, 0, 0, 0, 0};
+    const uint32_t first = blk * (kEnergyBlock * kEnergyWords) + threadIdx.x;
+#pragma unroll 4
+    for (int k = 0; k < kEnergyWords; ++k) {
+        const uint32_t s = first + (uint32_t)k * kEnergyBlock;
+        if (s < V) {
+            const uint32_t tau = fast_div(s, G.div_plane);
+            const uint32_t rem = s - tau * P;
+            const uint32_t y = fast_div(rem, G.div_row);
+            const uint32_t x = rem - y * L;
+            const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+            const uint32_t yp = (y + 1 == L) ? 0 : y + 1;
+            const uint32_t tp = (tau + 1 == G.Ltau) ? 0 : tau + 1;
+            const uint64_t w = S[s];
+            vadd(Csp, w ^ S[tau * P + y * L + xp] ^ G.Jx[rem]);
+            vadd(Csp, w ^ S[tau * P + yp * L + x] ^ G.Jy[rem]);
+            vadd(Ct, w ^ S[tp * P + rem]);
+            vadd(Cq, (w ^ (w >> 1)) & 0x5555555555555555ull);
+        }
+    }
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t my_sp = 0, my_t = 0, my_q = 0;
+#pragma unroll 1
+    for (uint32_t j = 0; j < 64; ++j) {
+        const uint32_t a = lane_total(Csp, j);
+        const uint32_t b = lane_total(Ct, j);
+        if (lane == j) { my_sp = a; my_t = b; }
+    }
+#pragma unroll 1
+    for (uint32_t p = 0; p < 32; ++p) {
+        const uint32_t c = lane_total(Cq, 2 * p);
+        if (lane == p) my_q = c;
+    }
+    int32_t* __restrict__ c = cnt + g * kCntStride;
+    if (my_sp) atomicAdd(&c[lane], (int32_t)my_sp);
+    if (my_t) atomicAdd(&c[64 + lane], (int32_t)my_t);
+    if (lane < 32 && my_q) atomicAdd(&c[128 + lane], (int32_t)my_q);
+}
+
+__global__ void __launch_bounds__(kEnergyBlock)
+k_energy(const GroupDev G, int32_t* cnt) {
+    energy_block(G, blockIdx.y, blockIdx.x, cnt);
+}
+
+__global__ void __launch_bounds__(kEnergyBlock)
+k_energy_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
+                 uint32_t n_groups) {
+    const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
+    const GroupDev G = groups[gi];
+    const uint32_t local = blockIdx.x - prefix[gi];
+    const uint32_t nb = energy_blocks_per_slot(G.V);
+    const uint32_t g = local / nb;
+    energy_block(G, g, local - g * nb, G.cnt);
+}
+
+// ---------------------------------------------------------------------------
+// Parallel tempering step of one group: 64 threads, thread j = lane j.
+// Turns the pass counters into bond sums, accumulates the measurement sums,
+// then visits pairs g = 0..N-2 in order; `cur` is the configuration that
+// currently sits at slot g (it may have arrived from g-1 in this step).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
+    const uint32_t j = threadIdx.x;
+    const uint32_t N = G.N;
+    if (N < 2) return;  // nothing to exchange
+    const int32_t V = (int32_t)G.V;
+    for (uint32_t g = 0; g < N; ++g) {
+        int32_t* c = G.cnt + g * kCntStride;
+        const int32_t bsp = 2 * V - 2 * c[j];
+        const int32_t bt = V - 2 * c[64 + j];
+        c[j] = 0;
+        c[64 + j] = 0;
+        G.E[(g * 64 + j) * 2 + 0] = bsp;
+        G.E[(g * 64 + j) * 2 + 1] = bt;
+        int64_t* sm = G.sums + (size_t)g * kSumStride;
+        sm[j] += bsp;
+        sm[64 + j] += bt;
+        if (j < 32) {
+            const int64_t q = (int64_t)V - 2 * (int64_t)c[128 + j];
+            c[128 + j] = 0;
+            sm[128 + j] += q;
+            sm[160 + j] += q * q;
+        }
+    }
+    int32_t cur_sp = G.E[j * 2 + 0], cur_t = G.E[j * 2 + 1];
+    uint32_t cur_w = G.walker[j];
+    uint64_t any = 0;
+    for (uint32_t g = 0; g + 1 < N; ++g) {
+        const int32_t nx_sp = G.E[((g + 1) * 64 + j) * 2 + 0];
+        const int32_t nx_t = G.E[((g + 1) * 64 + j) * 2 + 1];
+        const uint32_t nx_w = G.walker[(g + 1) * 64 + j];
+        const int32_t D = nx_t - cur_t;
+        bool accept;
+        if (G.sw_eq[g] || D >= 0) {
+            accept = true;
+        } else {
+            const uint32_t m = (uint32_t)(-D) >> 2;
+            const uint32_t th = (m >= 1 && m <= G.sw_len[g]) ? G.sw_thr[(size_t)g * G.sw_cap + (m - 1)] : 0u;
+            const uint4 o = philox(make_uint4(j >> 2, p, (1u << 24) | g, G.gid), G.key0, G.key1);
+            const uint32_t sel = j & 3u;
+            const uint32_t r = sel == 0 ? o.x : sel == 1 ? o.y : sel == 2 ? o.z : o.w;
+            accept = r <= th;
+        }
+        const uint64_t mask = __ballot((int)accept);
+        if (accept) {  // slot g takes the next configuration; cur moves up
+            G.E[(g * 64 + j) * 2 + 0] = nx_sp;
+            G.E[(g * 64 + j) * 2 + 1] = nx_t;
+            G.walker[g * 64 + j] = nx_w;
+        } else {       // cur stays at g; the next one becomes cur
+            G.E[(g * 64 + j) * 2 + 0] = cur_sp;
+            G.E[(g * 64 + j) * 2 + 1] = cur_t;
+            G.walker[g * 64 + j] = cur_w;
+            cur_sp = nx_sp;
+            cur_t = nx_t;
+            cur_w = nx_w;
+        }
+        if (j == 0) {
+            G.swaplog[(size_t)(p % G.log_cap) * (N - 1) + g] = mask;
+            G.acc[g] += (uint64_t)__popcll(mask);
+            G.lastmask[g] = mask;
+        }
+        any |= mask;
+    }
+    G.E[((N - 1) * 64 + j) * 2 + 0] = cur_sp;
+    G.E[((N - 1) * 64 + j) * 2 + 1] = cur_t;
+    G.walker[(N - 1) * 64 + j] = cur_w;
+    if (j == 0) G.lastmask[N - 1] = any ? 1ull : 0ull;
+
+    // round trips 0 -> N-1 -> 0; this step ends at PT time p+1
+    const uint32_t now = p + 1;
+    RoundTrip& r0 = G.rt[G.walker[j] * 64 + j];
+    if (r0.state == 2) {
+        r0.count += 1;
+        r0.sum += (uint64_t)(now - r0.t_last);
+        r0.t_last = now;
+        r0.state = 1;
+    } else if (r0.state == 0) {
+        r0.t_last = now;
+        r0.state = 1;
+    }
+    RoundTrip& rtop = G.rt[G.walker[(N - 1) * 64 + j] * 64 + j];
+    if (rtop.state == 1) rtop.state = 2;
+}
+
+__global__ void __launch_bounds__(64)
+k_pt(const GroupDev G, const uint32_t* __restrict__ ctr, uint32_t p_add) {
+    pt_group(G, ctr[1] + p_add);
+}
+
+__global__ void __launch_bounds__(64)
+k_pt_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ ctr, uint32_t p_add) {
+    const GroupDev G = groups[blockIdx.x];
+    pt_group(G, ctr[1] + p_add);
+}
+
+// Sweep and PT counters live on the device so that a captured graph can be
+// replayed: every launch reads them and adds its own offset.
+__global__ void k_advance(uint32_t* ctr, uint32_t dt, uint32_t dp) {
+    if (threadIdx.x == 0) {
+        ctr[0] += dt;
+        ctr[1] += dp;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Apply the accepted exchanges of the latest PT step to the spins: at every
+// site, the pairs' masked bit exchanges in ascending order (each word read
+// and written once).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void swap_site(const GroupDev& G, uint32_t site) {
+    const uint32_t N = G.N;
+    uint64_t* S = G.spins + site;
+    const size_t V = G.V;
+    uint64_t cur = S[0];  // running content of slot g
+    uint64_t orig = cur;  // what slot g held before this step
+    for (uint32_t g = 0; g + 1 < N; ++g) {
+        const uint64_t nx = S[(size_t)(g + 1) * V];
+        const uint64_t d = (cur ^ nx) & G.lastmask[g];
+        cur ^= d;
+        if (cur != orig) S[(size_t)g * V] = cur;
+        cur = nx ^ d;
+        orig = nx;
+    }
+    if (cur != orig) S[(size_t)(N - 1) * V] = cur;
+}
+
+__global__ void __launch_bounds__(kSwapBlock) k_swap_apply(const GroupDev G) {
+    if (G.N < 2 || G.lastmask[G.N - 1] == 0) return;
+    const uint32_t site = blockIdx.x * kSwapBlock + threadIdx.x;
+    if (site < G.V) swap_site(G, site);
+}
+
+__global__ void __launch_bounds__(kSwapBlock)
+k_swap_apply_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
+                     uint32_t n_groups) {
+    const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
+    const GroupDev G = groups[gi];
+    if (G.N < 2 || G.lastmask[G.N - 1] == 0) return;
+    const uint32_t site = (blockIdx.x - prefix[gi]) * kSwapBlock + threadIdx.x;
+    if (site < G.V) swap_site(G, site);
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation.
+// ---------------------------------------------------------------------------
+// Couplings: lane j has J_{i,d} = -1 iff bit 0 of word 0 of Philox with
+// counter (i, d, 3<<24, 0) under key j_seed[j] is set (i = x + L*y;
+// d = 0: +x bond, d = 1: +y bond).
+__global__ void k_init_couplings(const GroupDev G) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t P = G.L * G.L;
+    if (b >= 2 * P) return;
+    const uint32_t d = b / P, i = b - d * P;
+    uint64_t w = 0;
+    for (int j = 0; j < 64; ++j) {
+        const uint64_t key = G.jseed[j];
+        const uint4 o = philox(make_uint4(i, d, 3u << 24, 0u), (uint32_t)key, (uint32_t)(key >> 32));
+        w |= (uint64_t)(o.x & 1u) << j;
+    }
+    (d == 0 ? G.Jx : G.Jy)[i] = w;
+}
+
+// Spins: word(s, g) = o0 | o1<<32 of Philox with counter (s, 0, 2<<24 | g, gid).
+__global__ void k_init_spins(const GroupDev G) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t g = blockIdx.y;
+    if (s >= G.V) return;
+    const uint4 o = philox(make_uint4(s, 0u, (2u << 24) | g, G.gid), G.key0, G.key1);
+    G.spins[(size_t)g * G.V + s] = lo_hi(o.x, o.y);
+}
+
+// Walkers at their own slots, trackers, counters and sums cleared; walker 0
+// starts its clock at slot 0.
+__global__ void k_init_state(const GroupDev G) {
+    const uint32_t j = threadIdx.x;
+    const uint32_t N = G.N;
+    for (uint32_t g = 0; g < N; ++g) {
+        G.walker[g * 64 + j] = g;
+        RoundTrip r;
+        r.state = (g == 0) ? 1u : 0u;
+        r.t_last = 0;
+        r.count = 0;
+        r.pad = 0;
+        r.sum = 0;
+        G.rt[g * 64 + j] = r;
+        for (int k = j; k < kCntStride; k += 64) G.cnt[g * kCntStride + k] = 0;
+        for (int k = j; k < kSumStride; k += 64) G.sums[(size_t)g * kSumStride + k] = 0;
+        G.E[(g * 64 + j) * 2 + 0] = 0;
+        G.E[(g * 64 + j) * 2 + 1] = 0;
+    }
+    for (uint32_t g = j; g < N; g += 64) {
+        G.lastmask[g] = 0;
+        if (g + 1 < N) G.acc[g] = 0;
+    }
+    const size_t nlog = (size_t)G.log_cap * (N > 1 ? N - 1 : 1);
+    for (size_t i = j; i < nlog; i += 64) G.swaplog[i] = 0;
+}
+
+__global__ void k_zero32(uint32_t* p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_philox(const uint32_t* in, uint32_t* out, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t* a = in + 6 * (size_t)i;
+    const uint4 o = philox(make_uint4(a[0], a[1], a[2], a[3]), a[4], a[5]);
+    uint32_t* b = out + 4 * (size_t)i;
+    b[0] = o.x;
+    b[1] = o.y;
+    b[2] = o.z;
+    b[3] = o.w;
+}
+
+}  // namespace
+
+// ------------------------------- launchers ---------------------------------
+hipError_t launch_init_couplings(const GroupDev& g, hipStream_t s) {
+    const uint32_t n = 2 * g.L * g.L;
+    hipLaunchKernelGGL(k_init_couplings, dim3((n + 63) / 64), dim3(64), 0, s, g);
+    return hipGetLastError();
+}
+hipError_t launch_init_spins(const GroupDev& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_spins, dim3((g.V + 255) / 256, g.N), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+hipError_t launch_init_state(const GroupDev& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, g);
+    return hipGetLastError();
+}
+hipError_t launch_half_sweep(const GroupDev& g, uint32_t colour, const uint32_t* ctr,
+                             uint32_t t_add, hipStream_t s) {
+    hipLaunchKernelGGL(k_half_sweep, dim3(sweep_blocks_per_slot(g.V), g.N), dim3(kSweepBlock), 0, s,
+                       g, colour, ctr, t_add);
+    return hipGetLastError();
+}
+hipError_t launch_energy(const GroupDev& g, int32_t* cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy, dim3(energy_blocks_per_slot(g.V), g.N), dim3(kEnergyBlock), 0, s,
+                       g, cnt);
+    return hipGetLastError();
+}
+hipError_t launch_pt(const GroupDev& g, const uint32_t* ctr, uint32_t p_add, hipStream_t s) {
+    hipLaunchKernelGGL(k_pt, dim3(1), dim3(64), 0, s, g, ctr, p_add);
+    return hipGetLastError();
+}
+hipError_t launch_swap_apply(const GroupDev& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_swap_apply, dim3(swap_blocks(g.V)), dim3(kSwapBlock), 0, s, g);
+    return hipGetLastError();
+}
+hipError_t launch_zero32(void* p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (uint32_t*)p, n);
+    return hipGetLastError();
+}
+hipError_t launch_philox(const uint32_t* in, uint32_t* out, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox, dim3((n + 63) / 64), dim3(64), 0, s, in, out, n);
+    return hipGetLastError();
+}
+hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,
+                                     uint32_t t_add, hipStream_t s) {
+    if (plan.n_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_half_sweep_batched, dim3(plan.n_blocks), dim3(kSweepBlock), 0, s,
+                       plan.groups, plan.prefix, plan.n_groups, colour, ctr, t_add);
+    return hipGetLastError();
+}
+hipError_t launch_energy_batched(const BatchPlan& plan, hipStream_t s) {
+    if (plan.n_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_energy_batched, dim3(plan.n_blocks), dim3(kEnergyBlock), 0, s,
+                       plan.groups, plan.prefix, plan.n_groups);
+    return hipGetLastError();
+}
+hipError_t launch_pt_batched(const GroupDev* groups, uint32_t n_groups, const uint32_t* ctr,
+                             uint32_t p_add, hipStream_t s) {
+    if (n_groups == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pt_batched, dim3(n_groups), dim3(64), 0, s, groups, ctr, p_add);
+    return hipGetLastError();
+}
+hipError_t launch_advance(uint32_t* ctr, uint32_t dt, uint32_t dp, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, ctr, dt, dp);
+    return hipGetLastError();
+}
+hipError_t launch_swap_apply_batched(const BatchPlan& plan, hipStream_t s) {
+    if (plan.n_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_swap_apply_batched, dim3(plan.n_blocks), dim3(kSwapBlock), 0, s,
+                       plan.groups, plan.prefix, plan.n_groups);
+    return hipGetLastError();
+}
+
+}  // namespace qsg

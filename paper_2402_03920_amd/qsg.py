@@ -1,0 +1,344 @@
+"""Thin ctypes binding of libqsg.so (the C ABI in include/qsg.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels behind the C ABI.  PyTorch provides the device workspace (a uint8
+tensor) and the stream; nothing else.
+
+Functions keep their C names (qsg_create, qsg_sweep, ...).  `Ensemble`
+bundles the calls for one set of groups.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqsg.so")
+
+QSG_OK = 0
+QSG_E_INVALID = -1
+QSG_E_UNSUPPORTED = -2
+QSG_E_DEVICE = -3
+QSG_E_STATE = -4
+QSG_E_BUFFER = -5
+QSG_E_INTERRUPTED = -6
+
+QSG_PLAIN = 0
+QSG_BATCHED = 1
+QSG_GRAPH = 2
+QSG_NO_PT = 4
+
+QSG_M_ENERGY = 1
+QSG_M_OVERLAP = 2
+QSG_M_ACCEPT = 3
+QSG_M_WALKERS = 4
+QSG_M_SWAPLOG = 5
+QSG_M_ROUNDTRIP = 6
+QSG_M_SUMS = 7
+QSG_M_COUNTERS = 8
+
+SUM_STRIDE = 192
+
+
+class qsg_group_desc(C.Structure):
+    _fields_ = [("L", C.c_uint32), ("L_tau", C.c_uint32), ("beta", C.c_double),
+                ("n_gamma", C.c_uint32), ("group_id", C.c_uint32),
+                ("mc_seed", C.c_uint64), ("j_seed", C.c_uint64 * 64),
+                ("swap_table_cap", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class qsg_run_config(C.Structure):
+    _fields_ = [("pt_every", C.c_uint32), ("swaplog_cap", C.c_uint32)]
+
+
+ROUNDTRIP_DTYPE = np.dtype([("state", "<u4"), ("t_last", "<u4"), ("count", "<u4"),
+                            ("pad", "<u4"), ("sum", "<u8")])
+
+
+class QSGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"qsg error {code}: {msg}")
+        self.code = code
+
+
+_lib: Optional[C.CDLL] = None
+
+_SIGS = {
+    "qsg_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_uint32, C.c_void_p]),
+    "qsg_create": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t,
+                               C.c_void_p, C.POINTER(C.c_void_p)]),
+    "qsg_set_gamma_ladder": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p]),
+    "qsg_init_spins": (C.c_int32, [C.c_void_p]),
+    "qsg_sweep": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32]),
+    "qsg_pt_swap": (C.c_int32, [C.c_void_p]),
+    "qsg_measure": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t]),
+    "qsg_get_spins": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t]),
+    "qsg_set_spins": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t]),
+    "qsg_get_couplings": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "qsg_state_bytes": (C.c_size_t, [C.c_void_p]),
+    "qsg_get_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "qsg_set_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "qsg_get_tables": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]),
+    "qsg_build_tables": (C.c_int32, [C.c_double, C.c_uint32, C.c_uint32, C.c_void_p,
+                                     C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
+    "qsg_set_deadline": (C.c_int32, [C.c_void_p, C.c_double]),
+    "qsg_sync": (C.c_int32, [C.c_void_p]),
+    "qsg_last_error": (C.c_char_p, [C.c_void_p]),
+    "qsg_destroy": (None, [C.c_void_p]),
+    "qsg_philox": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
+}
+
+
+def lib() -> C.CDLL:
+    """Load libqsg.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2402_03920_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def _check(rc: int, ctx=None):
+    if rc != QSG_OK:
+        msg = lib().qsg_last_error(ctx)
+        raise QSGError(rc, msg.decode() if msg else "")
+
+
+# ------------------------------------------------------------ C-named calls
+def qsg_build_tables(beta: float, L_tau: int, gammas: Sequence[float], cap: int = 4096):
+    """Host table builder: (thr[N][15], equal[N-1], len[N-1], swap[N-1][cap])."""
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    N = g.size
+    pairs = max(N - 1, 1)
+    thr = np.zeros(N * 15, np.uint32)
+    eq = np.zeros(pairs, np.uint8)
+    ln = np.zeros(pairs, np.uint32)
+    sw = np.zeros(pairs * cap, np.uint32)
+    _check(lib().qsg_build_tables(float(beta), int(L_tau), N, _ptr(g), cap, _ptr(thr),
+                                  _ptr(eq), _ptr(ln), _ptr(sw)))
+    return thr.reshape(N, 15), eq[:N - 1], ln[:N - 1], sw.reshape(pairs, cap)[:N - 1]
+
+
+def make_desc(L, L_tau, beta, n_gamma, group_id, mc_seed, j_seeds,
+              swap_table_cap=0) -> qsg_group_desc:
+    d = qsg_group_desc()
+    d.L, d.L_tau, d.beta = int(L), int(L_tau), float(beta)
+    d.n_gamma, d.group_id, d.mc_seed = int(n_gamma), int(group_id), int(mc_seed)
+    seeds = list(j_seeds)
+    if len(seeds) != 64:
+        raise ValueError("64 coupling seeds per group")
+    for j, s in enumerate(seeds):
+        d.j_seed[j] = int(s)
+    d.swap_table_cap = int(swap_table_cap)
+    d.reserved = 0
+    return d
+
+
+class Ensemble:
+    """A set of groups on the current CUDA (HIP) device and stream.
+
+    `groups` are objects with L, L_tau, beta, gammas, group_id, mc_seed,
+    j_seeds (e.g. qsg_workloads.Group).
+    """
+
+    def __init__(self, groups: Sequence, pt_every: int = 10, swaplog_cap: int = 1024,
+                 swap_table_cap: int = 0, stream=None, device=None):
+        import torch  # device memory and streams only
+        self._torch = torch
+        L_ = lib()
+        self.groups = list(groups)
+        self.n = len(self.groups)
+        self.descs = (qsg_group_desc * self.n)()
+        for i, g in enumerate(self.groups):
+            self.descs[i] = make_desc(g.L, g.L_tau, g.beta, len(g.gammas), g.group_id,
+                                      g.mc_seed, g.j_seeds, swap_table_cap)
+        self.cfg = qsg_run_config(int(pt_every), int(swaplog_cap))
+        nbytes = L_.qsg_workspace_bytes(self.descs, self.n, C.byref(self.cfg))
+        if nbytes == 0:
+            raise QSGError(QSG_E_INVALID, "invalid group description")
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        # 256-byte alignment: torch's caching allocator returns >= 512-byte aligned blocks
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        assert self.workspace.data_ptr() % 256 == 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.ctx = C.c_void_p()
+        _check(L_.qsg_create(self.descs, self.n, C.byref(self.cfg),
+                             C.c_void_p(self.workspace.data_ptr()), nbytes,
+                             C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx)))
+        for i, g in enumerate(self.groups):
+            self.set_gamma_ladder(i, g.gammas)
+
+    # -- lifecycle
+    def close(self):
+        if self.ctx:
+            lib().qsg_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- calls
+    def set_gamma_ladder(self, i: int, gammas):
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+        if g.size != self.descs[i].n_gamma:
+            raise ValueError("ladder length differs from n_gamma")
+        _check(lib().qsg_set_gamma_ladder(self.ctx, i, _ptr(g)), self.ctx)
+
+    def init_spins(self):
+        _check(lib().qsg_init_spins(self.ctx), self.ctx)
+
+    def sweep(self, n: int, flags: int = QSG_PLAIN):
+        _check(lib().qsg_sweep(self.ctx, int(n), int(flags)), self.ctx)
+
+    def sweep_status(self, n: int, flags: int = QSG_PLAIN) -> int:
+        return int(lib().qsg_sweep(self.ctx, int(n), int(flags)))
+
+    def pt_swap(self):
+        _check(lib().qsg_pt_swap(self.ctx), self.ctx)
+
+    def sync(self):
+        _check(lib().qsg_sync(self.ctx), self.ctx)
+
+    def set_deadline(self, seconds: float):
+        _check(lib().qsg_set_deadline(self.ctx, float(seconds)), self.ctx)
+
+    def _measure(self, what, dtype, count):
+        out = np.zeros(count, dtype=dtype)
+        _check(lib().qsg_measure(self.ctx, what, _ptr(out), out.nbytes), self.ctx)
+        return out
+
+    def _split(self, flat, per_group):
+        res, off = [], 0
+        for i, g in enumerate(self.groups):
+            n, shape = per_group(len(g.gammas))
+            res.append(flat[off:off + n].reshape(shape))
+            off += n
+        return res
+
+    def energies(self) -> List[np.ndarray]:
+        """[(N, 64, 2) int32 (Bsp, Bt)] recomputed from the current spins."""
+        tot = sum(len(g.gammas) * 128 for g in self.groups)
+        flat = self._measure(QSG_M_ENERGY, np.int32, tot)
+        return self._split(flat, lambda N: (N * 128, (N, 64, 2)))
+
+    def overlaps(self) -> List[np.ndarray]:
+        tot = sum(len(g.gammas) * 32 for g in self.groups)
+        flat = self._measure(QSG_M_OVERLAP, np.int64, tot)
+        return self._split(flat, lambda N: (N * 32, (N, 32)))
+
+    def accepts(self) -> List[np.ndarray]:
+        tot = sum(max(len(g.gammas) - 1, 1) for g in self.groups)
+        flat = self._measure(QSG_M_ACCEPT, np.uint64, tot)
+        return [a[:len(g.gammas) - 1] for a, g in zip(
+            self._split(flat, lambda N: (max(N - 1, 1), (max(N - 1, 1),))), self.groups)]
+
+    def walkers(self) -> List[np.ndarray]:
+        tot = sum(len(g.gammas) * 64 for g in self.groups)
+        flat = self._measure(QSG_M_WALKERS, np.uint8, tot)
+        return self._split(flat, lambda N: (N * 64, (N, 64)))
+
+    def swaplog(self) -> List[np.ndarray]:
+        cap = self.cfg.swaplog_cap
+        tot = sum(cap * max(len(g.gammas) - 1, 1) for g in self.groups)
+        flat = self._measure(QSG_M_SWAPLOG, np.uint64, tot)
+        return self._split(flat, lambda N: (cap * max(N - 1, 1), (cap, max(N - 1, 1))))
+
+    def swaplog_rows(self) -> List[np.ndarray]:
+        """Masks of the PT steps done so far, oldest first (ring order)."""
+        p = self.counters()[1]
+        cap = self.cfg.swaplog_cap
+        n = min(p, cap)
+        idx = [(p - n + i) % cap for i in range(n)]
+        return [lg[idx].copy() for lg in self.swaplog()]
+
+    def roundtrips(self) -> List[np.ndarray]:
+        tot = sum(len(g.gammas) * 64 for g in self.groups)
+        flat = self._measure(QSG_M_ROUNDTRIP, ROUNDTRIP_DTYPE, tot)
+        return self._split(flat, lambda N: (N * 64, (N, 64)))
+
+    def sums(self) -> List[np.ndarray]:
+        tot = sum(len(g.gammas) * SUM_STRIDE for g in self.groups)
+        flat = self._measure(QSG_M_SUMS, np.int64, tot)
+        return self._split(flat, lambda N: (N * SUM_STRIDE, (N, SUM_STRIDE)))
+
+    def counters(self):
+        v = self._measure(QSG_M_COUNTERS, np.uint64, 2)
+        return int(v[0]), int(v[1])
+
+    def get_spins(self, i: int) -> np.ndarray:
+        g = self.groups[i]
+        out = np.zeros(len(g.gammas) * g.L_tau * g.L * g.L, dtype=np.uint64)
+        _check(lib().qsg_get_spins(self.ctx, i, _ptr(out), out.size), self.ctx)
+        return out
+
+    def set_spins(self, i: int, words: np.ndarray):
+        w = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
+        _check(lib().qsg_set_spins(self.ctx, i, _ptr(w), w.size), self.ctx)
+
+    def get_couplings(self, i: int):
+        L = self.groups[i].L
+        jx = np.zeros(L * L, np.uint64)
+        jy = np.zeros(L * L, np.uint64)
+        _check(lib().qsg_get_couplings(self.ctx, i, _ptr(jx), _ptr(jy)), self.ctx)
+        return jx, jy
+
+    def get_tables(self, i: int):
+        N = len(self.groups[i].gammas)
+        cap = self.descs[i].swap_table_cap or 4096
+        pairs = max(N - 1, 1)
+        thr = np.zeros(N * 15, np.uint32)
+        eq = np.zeros(pairs, np.uint8)
+        ln = np.zeros(pairs, np.uint32)
+        sw = np.zeros(pairs * cap, np.uint32)
+        _check(lib().qsg_get_tables(self.ctx, i, _ptr(thr), _ptr(eq), _ptr(ln), _ptr(sw)),
+               self.ctx)
+        return thr.reshape(N, 15), eq[:N - 1], ln[:N - 1], sw.reshape(pairs, cap)[:N - 1]
+
+    def get_state(self) -> np.ndarray:
+        n = lib().qsg_state_bytes(self.ctx)
+        out = np.zeros(n, np.uint8)
+        _check(lib().qsg_get_state(self.ctx, _ptr(out), n), self.ctx)
+        return out
+
+    def set_state(self, buf: np.ndarray):
+        b = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().qsg_set_state(self.ctx, _ptr(b), b.size), self.ctx)
+
+
+def philox_device(inputs: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 on the GPU for rows (ctr0..3, key0, key1)."""
+    import torch
+    a = np.ascontiguousarray(np.asarray(inputs, dtype=np.uint32)).reshape(-1, 6)
+    d_in = torch.from_numpy(a.view(np.int32).copy()).cuda()
+    d_out = torch.zeros((a.shape[0], 4), dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream()
+    _check(lib().qsg_philox(C.c_void_p(d_in.data_ptr()), C.c_void_p(d_out.data_ptr()),
+                            a.shape[0], C.c_void_p(s.cuda_stream)))
+    torch.cuda.synchronize()
+    return d_out.cpu().numpy().view(np.uint32)

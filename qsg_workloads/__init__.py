@@ -28,8 +28,10 @@ def geometric_ladder(gmin: float, gmax: float, n: int) -> np.ndarray:
     Generated once here (numpy float64) and handed as doubles to both the
     oracle and the library, so the two never disagree over libm rounding.
     """
-    if n < 2:
-        raise ValueError("a ladder needs at least two points")
+    if n < 1:
+        raise ValueError("a ladder needs at least one point")
+    if n == 1:
+        return np.array([float(gmin)])
     g = np.arange(n, dtype=np.float64)
     lad = gmin * (gmax / gmin) ** (g / (n - 1))
     lad[0] = gmin

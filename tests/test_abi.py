@@ -1,0 +1,107 @@
+"""CPU checks of the C ABI: the library loads, exports every declared
+symbol, validates its arguments, and its binary128 tables equal the
+oracle's mpmath tables entry for entry (no GPU needed for any of these)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import qsg_workloads as W
+from oracle import tables
+from paper_2402_03920_amd import qsg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(qsg_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = qsg.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _desc(**kw):
+    d = dict(L=8, L_tau=32, beta=4.0, n_gamma=16, group_id=0, mc_seed=42, j_seeds=[1] * 64)
+    d.update(kw)
+    return qsg.make_desc(**d)
+
+
+def _ws_bytes(desc, pt_every=10, cap=128):
+    arr = (qsg.qsg_group_desc * 1)(desc)
+    cfg = qsg.qsg_run_config(pt_every, cap)
+    return qsg.lib().qsg_workspace_bytes(arr, 1, C.byref(cfg))
+
+
+def test_workspace_validation():
+    assert _ws_bytes(_desc()) > 16 * 32 * 64 * 8
+    for bad in (dict(L=7), dict(L=0), dict(L_tau=3), dict(n_gamma=0), dict(n_gamma=65),
+                dict(beta=-1.0), dict(beta=float("nan"))):
+        assert _ws_bytes(_desc(**bad)) == 0, bad
+    assert _ws_bytes(_desc(), cap=0) == 0
+
+
+def test_create_rejects_bad_workspace_without_touching_the_device():
+    arr = (qsg.qsg_group_desc * 1)(_desc())
+    cfg = qsg.qsg_run_config(10, 16)
+    out = C.c_void_p()
+    rc = qsg.lib().qsg_create(arr, 1, C.byref(cfg), None, 0, None, C.byref(out))
+    assert rc == qsg.QSG_E_INVALID and not out.value
+    assert b"workspace" in qsg.lib().qsg_last_error(None)
+    rc = qsg.lib().qsg_create(arr, 1, C.byref(cfg), C.c_void_p(4096), 16, None, C.byref(out))
+    assert rc == qsg.QSG_E_BUFFER
+
+
+def test_host_tables_reject_bad_ladders():
+    with pytest.raises(qsg.QSGError) as e:
+        qsg.qsg_build_tables(4.0, 32, [2.0, 1.0])
+    assert e.value.code == qsg.QSG_E_INVALID
+    with pytest.raises(qsg.QSGError) as e:
+        qsg.qsg_build_tables(4.0, 32, [1.0, -1.0])
+    assert e.value.code == qsg.QSG_E_INVALID
+    # a tiny gap needs a long exchange table
+    with pytest.raises(qsg.QSGError) as e:
+        qsg.qsg_build_tables(128.0, 2048, [3.0, 3.0 + 1e-7], cap=64)
+    assert e.value.code == qsg.QSG_E_UNSUPPORTED
+
+
+def _ladders():
+    out = []
+    for g in W.c1_plain_small().groups:
+        out.append((g.beta, g.L_tau, g.gammas))
+    out.append((8.0, 128, W.geometric_ladder(2.0, 4.0, 32)))             # c2
+    for Lt, ng in ((64, 24), (128, 37), (256, 48)):                        # c3 shapes
+        out.append((Lt / 16.0, Lt, W.geometric_ladder(2.0, 4.0, ng)))
+    out.append((128.0, 2048, W.geometric_ladder(2.8, 3.6, 48)))          # c4
+    out.append((16.0, 256, W.geometric_ladder(2.0, 4.0, 32)))            # c5
+    out.append((1.0, 4, np.array([0.5, 0.5, 1.0, 60.0])))                 # equal pair, kp ~ 0
+    out.append((1.0, 4, np.array([1e-6, 0.3])))                           # frozen limit
+    return out
+
+
+@pytest.mark.parametrize("case", range(len(_ladders())))
+def test_binary128_tables_equal_oracle_mpmath(case):
+    beta, Lt, lad = _ladders()[case]
+    cap = 8192
+    thr, eq, ln, sw = qsg.qsg_build_tables(beta, Lt, lad, cap=cap)
+    othr = tables.metropolis_thresholds(beta, Lt, lad).reshape(len(lad), 15)
+    assert np.array_equal(thr, othr)
+    oeq, oln, otabs = tables.swap_tables(beta, Lt, lad)
+    assert np.array_equal(eq, oeq)
+    assert np.array_equal(ln, oln)
+    for g, t in enumerate(otabs):
+        assert np.array_equal(sw[g, :len(t)], t)
+        assert np.all(sw[g, len(t):] == 0)
