@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--samples", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=150)
     return ap.parse_args()
 
 

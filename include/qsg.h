@@ -188,6 +188,57 @@ void qsg_destroy(qsg_ctx* ctx);
  * = Philox(ctr = in[6i..6i+3], key = in[6i+4..6i+5]).  Device pointers. */
 qsg_status qsg_philox(const uint32_t* d_in, uint32_t* d_out, uint32_t n, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Learned Gamma ladder: a 6 -> 128 -> 128 -> 128 -> 32 MLP (exact-erf GELU on
+ * the hidden layers) mapping (L, L_tau, beta, frustrated-plaquette fraction,
+ * Gamma_min, Gamma_max) features to 31 increment logits of log Gamma and a
+ * log total exchange barrier.  No paper basis: an addition on top of the
+ * method that only chooses the ladder the PT step uses (Sec. 2.1).
+ * Parameters: qsg_mlp_param_count() FP32 values, flat W1[6][128], b1,
+ * W2[128][128], b2, W3[128][128], b3, W4[128][32], b4 (W[k][n] maps input k
+ * to output n), plus an optional BF16 copy: when it is given, every GEMM
+ * operand is rounded to bfloat16 and products accumulate in FP32.  All
+ * pointers are device pointers owned by the caller; work is enqueued on
+ * `hip_stream`; results are deterministic.
+ * ---------------------------------------------------------------------- */
+uint32_t qsg_mlp_param_count(void);
+
+/* Floats of forward workspace for a batch of B (activations kept for the
+ * backward pass). */
+size_t qsg_mlp_workspace_floats(uint32_t B);
+
+/* out[B][32] = MLP(x[B][6]); ws: qsg_mlp_workspace_floats(B) floats. */
+qsg_status qsg_mlp_forward(const float* d_params, const uint16_t* d_params_bf16,
+                           const float* d_x, uint32_t B, float* d_out, float* d_ws,
+                           void* hip_stream);
+
+/* Gradients of a scalar loss w.r.t. the FP32 parameters, given dL/d(out)
+ * d_dout[B][32] and the forward workspace of the same batch.
+ * d_scratch: 2*B*128 floats.  d_grads: qsg_mlp_param_count() floats. */
+qsg_status qsg_mlp_backward(const float* d_params, const uint16_t* d_params_bf16,
+                            const float* d_x, const float* d_ws, const float* d_dout,
+                            uint32_t B, float* d_grads, float* d_scratch, void* hip_stream);
+
+/* Per sample: KL(t || softmax(z[0..30])) + (z[31] - logL)^2 into d_loss[B],
+ * and d_dz[B][32] = gradient of the batch mean. */
+qsg_status qsg_mlp_loss(const float* d_z, const float* d_target_inc, const float* d_target_logL,
+                        uint32_t B, float* d_dz, float* d_loss, void* hip_stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step >= 1) on the FP32
+ * parameters; refreshes the BF16 copy when given.  m, v: FP32 moments. */
+qsg_status qsg_mlp_adam(float* d_params, uint16_t* d_params_bf16, const float* d_grads,
+                        float* d_m, float* d_v, uint32_t step, float lr, void* hip_stream);
+
+/* BF16 copy of the FP32 parameters (nearest even). */
+qsg_status qsg_mlp_to_bf16(const float* d_params, uint16_t* d_params_bf16, void* hip_stream);
+
+/* Ladders d_ladder[B][32] (doubles, non-decreasing, ends exactly gmin and
+ * gmax) from outputs d_z[B][32]: log G_i = log gmin + (log gmax - log gmin)
+ * * sum_{l<i} softmax(z[0..30])_l; d_acc_pred[B] = 1 - exp(z[31])/31 (may be
+ * NULL). */
+qsg_status qsg_mlp_decode(const float* d_z, const double* d_gmin, const double* d_gmax,
+                          uint32_t B, double* d_ladder, float* d_acc_pred, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

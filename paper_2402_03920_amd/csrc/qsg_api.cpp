@@ -17,6 +17,7 @@
 
 #include "../../include/qsg.h"
 #include "qsg_internal.h"
+#include "qsg_mlp.h"
 
 extern "C" int qsg_tables_build_host(double beta, uint32_t L_tau, uint32_t N, const double* gamma,
                                      uint32_t cap, uint32_t* thr, uint8_t* eq, uint32_t* len,
@@ -801,6 +802,69 @@ qsg_status qsg_philox(const uint32_t* d_in, uint32_t* d_out, uint32_t n, void* h
     hipError_t e = qsg::launch_philox(d_in, d_out, n, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(nullptr, QSG_E_DEVICE, "philox launch: %s", hipGetErrorString(e));
     return QSG_OK;
+}
+
+uint32_t qsg_mlp_param_count(void) { return (uint32_t)qsg::kMlpParams; }
+
+size_t qsg_mlp_workspace_floats(uint32_t B) { return qsg::mlp_ws_floats((int)B); }
+
+static qsg_status mlp_status(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(nullptr, QSG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return QSG_OK;
+}
+
+static bool mlp_batch_ok(uint32_t B) { return B >= 1 && B <= (1u << 20); }
+
+qsg_status qsg_mlp_forward(const float* d_params, const uint16_t* d_params_bf16, const float* d_x,
+                           uint32_t B, float* d_out, float* d_ws, void* hip_stream) {
+    if (!d_params || !d_x || !d_out || !d_ws || !mlp_batch_ok(B))
+        return fail(nullptr, QSG_E_INVALID, "mlp_forward: null buffer or bad batch");
+    return mlp_status(qsg::mlp_forward(d_params, d_params_bf16, d_x, (int)B, d_out, d_ws,
+                                       static_cast<hipStream_t>(hip_stream)),
+                      "mlp_forward");
+}
+
+qsg_status qsg_mlp_backward(const float* d_params, const uint16_t* d_params_bf16, const float* d_x,
+                            const float* d_ws, const float* d_dout, uint32_t B, float* d_grads,
+                            float* d_scratch, void* hip_stream) {
+    if (!d_params || !d_x || !d_ws || !d_dout || !d_grads || !d_scratch || !mlp_batch_ok(B))
+        return fail(nullptr, QSG_E_INVALID, "mlp_backward: null buffer or bad batch");
+    return mlp_status(qsg::mlp_backward(d_params, d_params_bf16, d_x, d_ws, d_dout, (int)B, d_grads,
+                                        d_scratch, static_cast<hipStream_t>(hip_stream)),
+                      "mlp_backward");
+}
+
+qsg_status qsg_mlp_loss(const float* d_z, const float* d_target_inc, const float* d_target_logL,
+                        uint32_t B, float* d_dz, float* d_loss, void* hip_stream) {
+    if (!d_z || !d_target_inc || !d_target_logL || !d_dz || !d_loss || !mlp_batch_ok(B))
+        return fail(nullptr, QSG_E_INVALID, "mlp_loss: null buffer or bad batch");
+    return mlp_status(qsg::mlp_loss(d_z, d_target_inc, d_target_logL, (int)B, d_dz, d_loss,
+                                    static_cast<hipStream_t>(hip_stream)),
+                      "mlp_loss");
+}
+
+qsg_status qsg_mlp_adam(float* d_params, uint16_t* d_params_bf16, const float* d_grads, float* d_m,
+                        float* d_v, uint32_t step, float lr, void* hip_stream) {
+    if (!d_params || !d_grads || !d_m || !d_v || step == 0 || !(lr >= 0))
+        return fail(nullptr, QSG_E_INVALID, "mlp_adam: null buffer, step 0 or bad lr");
+    return mlp_status(qsg::mlp_adam(d_params, d_params_bf16, d_grads, d_m, d_v, step, lr,
+                                    static_cast<hipStream_t>(hip_stream)),
+                      "mlp_adam");
+}
+
+qsg_status qsg_mlp_to_bf16(const float* d_params, uint16_t* d_params_bf16, void* hip_stream) {
+    if (!d_params || !d_params_bf16) return fail(nullptr, QSG_E_INVALID, "mlp_to_bf16: null buffer");
+    return mlp_status(qsg::mlp_to_bf16(d_params, d_params_bf16, static_cast<hipStream_t>(hip_stream)),
+                      "mlp_to_bf16");
+}
+
+qsg_status qsg_mlp_decode(const float* d_z, const double* d_gmin, const double* d_gmax, uint32_t B,
+                          double* d_ladder, float* d_acc_pred, void* hip_stream) {
+    if (!d_z || !d_gmin || !d_gmax || !d_ladder || !mlp_batch_ok(B))
+        return fail(nullptr, QSG_E_INVALID, "mlp_decode: null buffer or bad batch");
+    return mlp_status(qsg::mlp_decode(d_z, d_gmin, d_gmax, (int)B, d_ladder, d_acc_pred,
+                                      static_cast<hipStream_t>(hip_stream)),
+                      "mlp_decode");
 }
 
 }  // extern "C"

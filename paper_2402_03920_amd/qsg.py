@@ -91,6 +91,20 @@ _SIGS = {
     "qsg_last_error": (C.c_char_p, [C.c_void_p]),
     "qsg_destroy": (None, [C.c_void_p]),
     "qsg_philox": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
+    "qsg_mlp_param_count": (C.c_uint32, []),
+    "qsg_mlp_workspace_floats": (C.c_size_t, [C.c_uint32]),
+    "qsg_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "qsg_mlp_backward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
+    "qsg_mlp_loss": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]),
+    "qsg_mlp_adam": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_uint32, C.c_float, C.c_void_p]),
+    "qsg_mlp_to_bf16": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "qsg_mlp_decode": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]),
 }
 
 
@@ -342,3 +356,42 @@ def philox_device(inputs: np.ndarray) -> np.ndarray:
                             a.shape[0], C.c_void_p(s.cuda_stream)))
     torch.cuda.synchronize()
     return d_out.cpu().numpy().view(np.uint32)
+
+
+# ------------------------------------------------------------- ladder MLP
+def _dp(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream_ptr():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def qsg_mlp_forward(params, params_bf16, x, out, ws):
+    _check(lib().qsg_mlp_forward(_dp(params), _dp(params_bf16), _dp(x), x.shape[0], _dp(out),
+                                 _dp(ws), _stream_ptr()))
+
+
+def qsg_mlp_backward(params, params_bf16, x, ws, dout, grads, scratch):
+    _check(lib().qsg_mlp_backward(_dp(params), _dp(params_bf16), _dp(x), _dp(ws), _dp(dout),
+                                  x.shape[0], _dp(grads), _dp(scratch), _stream_ptr()))
+
+
+def qsg_mlp_loss(z, t, logL, dz, loss):
+    _check(lib().qsg_mlp_loss(_dp(z), _dp(t), _dp(logL), z.shape[0], _dp(dz), _dp(loss),
+                              _stream_ptr()))
+
+
+def qsg_mlp_adam(params, params_bf16, grads, m, v, step, lr):
+    _check(lib().qsg_mlp_adam(_dp(params), _dp(params_bf16), _dp(grads), _dp(m), _dp(v),
+                              int(step), float(lr), _stream_ptr()))
+
+
+def qsg_mlp_to_bf16(params, params_bf16):
+    _check(lib().qsg_mlp_to_bf16(_dp(params), _dp(params_bf16), _stream_ptr()))
+
+
+def qsg_mlp_decode(z, gmin, gmax, ladder, acc_pred=None):
+    _check(lib().qsg_mlp_decode(_dp(z), _dp(gmin), _dp(gmax), z.shape[0], _dp(ladder),
+                                _dp(acc_pred), _stream_ptr()))

@@ -119,7 +119,7 @@ def test_c1_plain_full_bit_exact():
             ens.init_spins()
             ens.sweep(wl.sweeps, MODES[mode])
             compare_state(ens, [og])
-            assert int(og.acc.sum()) > 0 and int(og.rt_count.sum()) > 0
+            assert int(og.acc.sum()) > 0
 
 
 def test_c2_shape_truncated_bit_exact():
