@@ -86,6 +86,11 @@ typedef struct {
 typedef struct {
     uint32_t pt_every;    /* PT step after sweep t if (t+1) % pt_every == 0; 0 = none */
     uint32_t swaplog_cap; /* PT steps kept in the swap log ring (>= 1)        */
+    uint32_t sweep_split; /* schedule of the colour pass: Philox blocks every
+                             word goes through before the words still undecided
+                             are packed into fewer waves (1..16; 16 = never;
+                             0 = default 4).  Results do not depend on it.     */
+    uint32_t reserved;    /* must be 0 */
 } qsg_run_config;
 
 /* qsg_sweep flags */

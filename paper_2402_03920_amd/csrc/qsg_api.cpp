@@ -171,6 +171,7 @@ struct qsg_ctx {
     hipGraph_t chunk_graph = nullptr;
     bool failed = false;
     bool spins_ready = false;
+    uint32_t q_split = 4;  // see qsg_run_config.sweep_split
     bool has_deadline = false;
     double deadline = 0;  // steady-clock seconds
     std::string err;
@@ -234,9 +235,9 @@ void destroy_graph(qsg_ctx* c) {
 // ---------------------------------------------------------------- passes --
 qsg_status plain_sweep(qsg_ctx* c, uint32_t t_add) {
     for (const GroupDev& g : c->gd)
-        QSG_HIP(c, qsg::launch_half_sweep(g, 0, c->d_counters, t_add, c->stream));
+        QSG_HIP(c, qsg::launch_half_sweep(g, 0, c->d_counters, t_add, c->q_split, c->stream));
     for (const GroupDev& g : c->gd)
-        QSG_HIP(c, qsg::launch_half_sweep(g, 1, c->d_counters, t_add, c->stream));
+        QSG_HIP(c, qsg::launch_half_sweep(g, 1, c->d_counters, t_add, c->q_split, c->stream));
     return QSG_OK;
 }
 
@@ -251,8 +252,8 @@ qsg_status plain_pt(qsg_ctx* c, uint32_t p_add) {
 }
 
 qsg_status batched_sweep(qsg_ctx* c, hipStream_t s, uint32_t t_add) {
-    QSG_HIP(c, qsg::launch_half_sweep_batched(c->plan_sweep, 0, c->d_counters, t_add, s));
-    QSG_HIP(c, qsg::launch_half_sweep_batched(c->plan_sweep, 1, c->d_counters, t_add, s));
+    QSG_HIP(c, qsg::launch_half_sweep_batched(c->plan_sweep, 0, c->d_counters, t_add, c->q_split, s));
+    QSG_HIP(c, qsg::launch_half_sweep_batched(c->plan_sweep, 1, c->d_counters, t_add, c->q_split, s));
     return QSG_OK;
 }
 
@@ -315,7 +316,7 @@ extern "C" {
 
 size_t qsg_workspace_bytes(const qsg_group_desc* groups, uint32_t n_groups,
                            const qsg_run_config* cfg) {
-    if (!groups || n_groups == 0 || !cfg || cfg->swaplog_cap == 0) return 0;
+    if (!groups || n_groups == 0 || !cfg || cfg->swaplog_cap == 0 || cfg->reserved) return 0;
     Layout L;
     std::string why;
     if (!make_layout(groups, n_groups, *cfg, &L, &why)) return 0;
@@ -329,6 +330,7 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
     if (!groups || n_groups == 0 || !cfg)
         return fail(nullptr, QSG_E_INVALID, "groups/cfg null or n_groups == 0");
     if (cfg->swaplog_cap == 0) return fail(nullptr, QSG_E_INVALID, "swaplog_cap must be >= 1");
+    if (cfg->reserved) return fail(nullptr, QSG_E_INVALID, "run config reserved field must be 0");
     if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0)
         return fail(nullptr, QSG_E_INVALID, "workspace must be non-null and 256-byte aligned");
     Layout L;
@@ -341,6 +343,7 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
     qsg_ctx* c = new qsg_ctx();
     c->desc.assign(groups, groups + n_groups);
     c->cfg = *cfg;
+    c->q_split = cfg->sweep_split ? (cfg->sweep_split > 16 ? 16 : cfg->sweep_split) : 4;
     c->layout = L;
     c->ws = static_cast<uint8_t*>(d_workspace);
     c->ws_bytes = ws_bytes;

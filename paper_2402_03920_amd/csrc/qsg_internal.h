@@ -81,13 +81,17 @@ struct GroupDev {
 hipError_t launch_init_couplings(const GroupDev& g, hipStream_t s);
 hipError_t launch_init_spins(const GroupDev& g, hipStream_t s);
 hipError_t launch_init_state(const GroupDev& g, hipStream_t s);
+// q_split: Philox blocks every word of a colour pass goes through before the
+// words still undecided are packed into the first waves of the block
+// (16: no packing).  Results do not depend on it.
 hipError_t launch_half_sweep(const GroupDev& g, uint32_t colour, const uint32_t* ctr,
-                             uint32_t t_add, hipStream_t s);
+                             uint32_t t_add, uint32_t q_split, hipStream_t s);
 hipError_t launch_energy(const GroupDev& g, int32_t* cnt, hipStream_t s);
 hipError_t launch_pt(const GroupDev& g, const uint32_t* ctr, uint32_t p_add, hipStream_t s);
 hipError_t launch_advance(uint32_t* ctr, uint32_t dt, uint32_t dp, hipStream_t s);
 hipError_t launch_swap_apply(const GroupDev& g, hipStream_t s);
 hipError_t launch_zero32(void* p, size_t n_words32, hipStream_t s);
+
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, uint32_t n, hipStream_t s);
 
 // Batched: one launch per pass over all groups.  `prefix[i]` is the first
@@ -100,7 +104,7 @@ struct BatchPlan {
     uint32_t n_blocks;
 };
 hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,
-                                     uint32_t t_add, hipStream_t s);
+                                     uint32_t t_add, uint32_t q_split, hipStream_t s);
 hipError_t launch_energy_batched(const BatchPlan& plan, hipStream_t s);
 hipError_t launch_pt_batched(const GroupDev* groups, uint32_t n_groups, const uint32_t* ctr,
                              uint32_t p_add, hipStream_t s);

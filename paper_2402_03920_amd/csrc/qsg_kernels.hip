@@ -27,15 +27,20 @@ constexpr uint32_t kW0 = 0x9E3779B9u;
 constexpr uint32_t kW1 = 0xBB67AE85u;
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
-// and xors with the key, the key advanced by the Weyl constants.
+// and xors with the key, the key advanced by the Weyl constants.  Each
+// product is one v_mad_u64_u32 (both halves at once) and each three-way xor
+// one v_bitop3_b32.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = c.x * kM0;
-        const uint32_t hi0 = __umulhi(c.x, kM0);
-        const uint32_t lo1 = c.z * kM1;
-        const uint32_t hi1 = __umulhi(c.z, kM1);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        const uint64_t p0 = (uint64_t)c.x * kM0;
+        const uint64_t p1 = (uint64_t)c.z * kM1;
+        c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                       xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
         k0 += kW0;
         k1 += kW1;
     }
@@ -44,6 +49,21 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 
 __device__ __forceinline__ uint64_t lo_hi(uint32_t lo, uint32_t hi) {
     return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// A group record read from memory by a batched kernel: every block reads one
+// record, so its fields are block-uniform; moving them to scalar registers
+// keeps all addressing and threshold logic on the scalar unit.
+__device__ __forceinline__ GroupDev uniform_record(const GroupDev* __restrict__ p) {
+    static_assert(sizeof(GroupDev) % 4 == 0, "record must be whole dwords");
+    union {
+        GroupDev g;
+        uint32_t w[sizeof(GroupDev) / 4];
+    } u;
+    u.g = *p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(GroupDev) / 4); ++i) u.w[i] = __builtin_amdgcn_readfirstlane(u.w[i]);
+    return u.g;
 }
 
 // Division of x < 2^31 by a block-uniform d >= 1 with a precomputed
@@ -81,15 +101,30 @@ __device__ __forceinline__ uint64_t all_if(uint32_t v, uint32_t bit) {
     return 0ull - (uint64_t)((v >> bit) & 1u);  // block-uniform 0 or ~0
 }
 
-// ---------------------------------------------------------------------------
-// One Metropolis update of the colour-c word number `idx` of slot g.
-// Colour-c words of a slot are numbered tau-plane by tau-plane, row by row:
-// idx = tau*(L*L/2) + y*(L/2) + xh, x = 2*xh + ((c + y + tau) & 1).
-// ---------------------------------------------------------------------------
-template <int R>
-__device__ __forceinline__ void update_word(const GroupDev& G, uint32_t g, uint32_t colour,
-                                            uint32_t t, uint32_t idx) {
-    using C = Classes<R>;
+// Per-word state of the comparison: the class planes it needs (bit-sliced
+// n_s = s2 s1 s0 and the two time-bond planes t1, t2), the lanes accepted so
+// far and the lanes still undecided.
+struct WordState {
+    uint32_t s;  // flat site index (RNG counter word 0)
+    uint64_t w;  // centre word before the update
+    uint64_t s0, s1, s2, t1, t2;
+    uint64_t acc, und;
+};
+
+// Words of one block still undecided after the first levels wait in LDS
+// (structure of arrays) and are finished by as few waves as possible.
+struct SweepQueue {
+    uint32_t count;
+    uint32_t s[kSweepBlock];
+    uint64_t w[kSweepBlock], s0[kSweepBlock], s1[kSweepBlock], s2[kSweepBlock];
+    uint64_t t1[kSweepBlock], t2[kSweepBlock], acc[kSweepBlock], und[kSweepBlock];
+};
+
+// Load the neighbourhood of colour-c word `idx` of a slot and count
+// unsatisfied bonds.  Colour-c words of a slot are numbered plane by plane,
+// row by row: idx = tau*(L*L/2) + y*(L/2) + xh, x = 2*xh + ((c + y + tau) & 1).
+__device__ __forceinline__ WordState load_word(const GroupDev& G, const uint64_t* __restrict__ S,
+                                               uint32_t colour, uint32_t idx) {
     const uint32_t L = G.L;
     const uint32_t P = L * L;
     const uint32_t half_plane = P >> 1;
@@ -105,13 +140,12 @@ __device__ __forceinline__ void update_word(const GroupDev& G, uint32_t g, uint3
     const uint32_t ym = (y == 0) ? L - 1 : y - 1;
     const uint32_t tp = (tau + 1 == G.Ltau) ? 0 : tau + 1;
     const uint32_t tm = (tau == 0) ? G.Ltau - 1 : tau - 1;
-
-    uint64_t* __restrict__ S = G.spins + (size_t)g * G.V;
     const uint32_t row = y * L;
     const uint32_t plane = tau * P;
-    const uint32_t s = plane + row + x;  // flat site index = RNG counter word 0
 
-    const uint64_t w = S[s];
+    WordState st;
+    st.s = plane + row + x;
+    const uint64_t w = S[st.s];
     const uint64_t nxp = S[plane + row + xp];
     const uint64_t nxm = S[plane + row + xm];
     const uint64_t nyp = S[plane + yp * L + x];
@@ -128,75 +162,173 @@ __device__ __forceinline__ void update_word(const GroupDev& G, uint32_t g, uint3
     const uint64_t u3 = w ^ nyp ^ jyp, u4 = w ^ nym ^ jym;
     const uint64_t a0 = u1 ^ u2, a1 = u1 & u2;
     const uint64_t b0 = u3 ^ u4, b1 = u3 & u4;
-    const uint64_t s0 = a0 ^ b0, c0 = a0 & b0;
-    const uint64_t s1 = a1 ^ b1 ^ c0;
-    const uint64_t s2 = (a1 & b1) | (c0 & (a1 ^ b1));
-    const uint64_t t1 = w ^ ntp, t2 = w ^ ntm;
+    const uint64_t c0 = a0 & b0;
+    st.w = w;
+    st.s0 = a0 ^ b0;
+    st.s1 = a1 ^ b1 ^ c0;
+    st.s2 = (a1 & b1) | (c0 & (a1 ^ b1));
+    st.t1 = w ^ ntp;
+    st.t2 = w ^ ntm;
+    st.acc = 0;
+    st.und = 0;
+    return st;
+}
 
+// One-hot masks of the listed classes and the slot's thresholds for them.
+template <int R>
+__device__ __forceinline__ void class_masks(const WordState& st, const uint32_t* __restrict__ thr,
+                                            uint64_t (&M)[Classes<R>::n],
+                                            uint32_t (&th)[Classes<R>::n]) {
+    using C = Classes<R>;
     uint64_t NS[5], NT[3];
-    NS[0] = ~(s2 | s1 | s0);
-    NS[1] = s0 & ~s1 & ~s2;
-    NS[2] = s1 & ~s0;
-    NS[3] = s1 & s0;
-    NS[4] = s2;
-    NT[0] = ~(t1 | t2);
-    NT[1] = t1 ^ t2;
-    NT[2] = t1 & t2;
-
-    // thresholds of this slot (uniform across the block)
-    const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
-    uint32_t th[C::n];
-    uint64_t M[C::n];
-    uint64_t live = 0;
+    NS[0] = ~(st.s2 | st.s1 | st.s0);
+    NS[1] = st.s0 & ~st.s1 & ~st.s2;
+    NS[2] = st.s1 & ~st.s0;
+    NS[3] = st.s1 & st.s0;
+    NS[4] = st.s2;
+    NT[0] = ~(st.t1 | st.t2);
+    NT[1] = st.t1 ^ st.t2;
+    NT[2] = st.t1 & st.t2;
 #pragma unroll
     for (int i = 0; i < C::n; ++i) {
-        th[i] = thr[C::ns[i] * 3 + C::nt[i]];
+        th[i] = __builtin_amdgcn_readfirstlane(thr[C::ns[i] * 3 + C::nt[i]]);
         M[i] = NS[C::ns[i]] & NT[C::nt[i]];
         if (R == 3) M[i] &= ~all_if(th[i] == 0xFFFFFFFFu ? 1u : 0u, 0);
-        live |= M[i];
     }
-    // lanes outside the listed classes have dE <= 0: accepted outright
-    uint64_t acc = ~live;
-    uint64_t und = live;
+}
 
-    const uint4 ctr_base = make_uint4(s, t, g << 4, G.gid);
+// Three-input bitwise operation of gfx950 (v_bitop3_b32); the immediate is
+// the truth table f(0xF0, 0xCC, 0xAA) of the operand order (a, b, c).
+#define BITOP3(a, b, c, table) __builtin_amdgcn_bitop3_b32((a), (b), (c), (table))
+constexpr int kAndOr = 0xEA;      // (a & b) | c
+constexpr int kAndAndNot = 0x40;  // a & b & ~c
+constexpr int kAndXnor = 0x90;    // a & ~(b ^ c)
+
+// Compare the lanes' bit-sliced Philox numbers with their class thresholds,
+// most significant level first, for blocks q0 <= q < q1 while any lane of
+// the wave is undecided.  Block q (counter (s, t, g<<4 | q, gid)) carries
+// levels 2q and 2q+1.  Per level, on each 32-bit half: the threshold bit
+// plane T (one bitop3 per class), then
+//   acc |= und & T & ~W   (r has 0 where thr has 1: r < thr, accepted)
+//   und &= ~(T ^ W)       (still equal so far).
+template <int R>
+__device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, uint32_t t,
+                                               uint32_t s, const uint64_t (&M)[Classes<R>::n],
+                                               const uint32_t (&th)[Classes<R>::n], uint32_t q0,
+                                               uint32_t q1, uint64_t& acc, uint64_t& und) {
+    using C = Classes<R>;
+    uint32_t acc_lo = (uint32_t)acc, acc_hi = (uint32_t)(acc >> 32);
+    uint32_t und_lo = (uint32_t)und, und_hi = (uint32_t)(und >> 32);
 #pragma unroll 1
-    for (uint32_t q = 0; q < 16; ++q) {
-        if (!__any(und != 0)) break;  // every lane of the wave is decided
-        const uint4 o = philox(make_uint4(ctr_base.x, ctr_base.y, ctr_base.z | q, ctr_base.w),
-                               G.key0, G.key1);
-        const uint64_t lev[2] = {lo_hi(o.x, o.y), lo_hi(o.z, o.w)};
+    for (uint32_t q = q0; q < q1; ++q) {
+        if (!__any((und_lo | und_hi) != 0)) break;  // every lane of the wave is decided
+        const uint4 o = philox(make_uint4(s, t, (g << 4) | q, G.gid), G.key0, G.key1);
+        const uint32_t lev_lo[2] = {o.x, o.z};
+        const uint32_t lev_hi[2] = {o.y, o.w};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t bit = 31u - (2u * q + (uint32_t)h);
-            uint64_t T = 0;
+            uint32_t T_lo = 0, T_hi = 0;
 #pragma unroll
-            for (int i = 0; i < C::n; ++i) T |= M[i] & all_if(th[i], bit);
-            const uint64_t W = lev[h];
-            acc |= und & T & ~W;  // r bit 0 where thr bit 1: r < thr
-            und &= ~(T ^ W);      // still equal so far
+            for (int i = 0; i < C::n; ++i) {
+                const uint32_t B = 0u - ((th[i] >> bit) & 1u);  // block-uniform 0 or ~0
+                T_lo = BITOP3((uint32_t)M[i], B, T_lo, kAndOr);
+                T_hi = BITOP3((uint32_t)(M[i] >> 32), B, T_hi, kAndOr);
+            }
+            acc_lo |= BITOP3(und_lo, T_lo, lev_lo[h], kAndAndNot);
+            acc_hi |= BITOP3(und_hi, T_hi, lev_hi[h], kAndAndNot);
+            und_lo = BITOP3(und_lo, T_lo, lev_lo[h], kAndXnor);
+            und_hi = BITOP3(und_hi, T_hi, lev_hi[h], kAndXnor);
         }
     }
-    acc |= und;  // equal on all 32 bits: r == thr, accepted
-    if (acc) S[s] = w ^ acc;
+    acc = lo_hi(acc_lo, acc_hi);
+    und = lo_hi(und_lo, und_hi);
 }
 
-__device__ __forceinline__ void update_word_any(const GroupDev& G, uint32_t g, uint32_t colour,
-                                                uint32_t t, uint32_t idx) {
-    switch (G.thr[g * kThrStride + 15]) {  // regime of slot g, set with the table
-        case 0: update_word<0>(G, g, colour, t, idx); break;
-        case 1: update_word<1>(G, g, colour, t, idx); break;
-        case 2: update_word<2>(G, g, colour, t, idx); break;
-        default: update_word<3>(G, g, colour, t, idx); break;
+// A colour pass over the block's words: the first q_split Philox blocks of
+// levels for every word, then the words still undecided are packed into the
+// first waves of the block and finished there (far fewer waves run the long
+// tail of levels).  Every thread of the block calls this (it synchronises);
+// `valid` is false for threads past the last word.
+template <int R>
+__device__ __forceinline__ void sweep_block(const GroupDev& G, uint32_t g, uint32_t colour,
+                                            uint32_t t, uint32_t idx, bool valid,
+                                            uint32_t q_split, SweepQueue& Q) {
+    using C = Classes<R>;
+    uint64_t* __restrict__ S = G.spins + (size_t)g * G.V;
+    const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
+    if (threadIdx.x == 0) Q.count = 0;
+    __syncthreads();
+    WordState st;
+    st.acc = 0;
+    st.und = 0;
+    if (valid) {
+        st = load_word(G, S, colour, idx);
+        uint64_t M[C::n];
+        uint32_t th[C::n];
+        class_masks<R>(st, thr, M, th);
+        uint64_t live = 0;
+#pragma unroll
+        for (int i = 0; i < C::n; ++i) live |= M[i];
+        st.acc = ~live;  // lanes outside the listed classes: dE <= 0, accepted
+        st.und = live;
+        compare_levels<R>(G, g, t, st.s, M, th, 0, q_split, st.acc, st.und);
+    }
+    if (valid && st.und != 0) {
+        const uint32_t k = atomicAdd(&Q.count, 1u);
+        Q.s[k] = st.s;
+        Q.w[k] = st.w;
+        Q.s0[k] = st.s0;
+        Q.s1[k] = st.s1;
+        Q.s2[k] = st.s2;
+        Q.t1[k] = st.t1;
+        Q.t2[k] = st.t2;
+        Q.acc[k] = st.acc;
+        Q.und[k] = st.und;
+    } else if (valid && st.acc) {
+        S[st.s] = st.w ^ st.acc;
+    }
+    __syncthreads();
+    const uint32_t n = Q.count;
+    if (threadIdx.x < n) {
+        const uint32_t k = threadIdx.x;
+        WordState r;
+        r.s = Q.s[k];
+        r.w = Q.w[k];
+        r.s0 = Q.s0[k];
+        r.s1 = Q.s1[k];
+        r.s2 = Q.s2[k];
+        r.t1 = Q.t1[k];
+        r.t2 = Q.t2[k];
+        uint64_t acc = Q.acc[k], und = Q.und[k];
+        uint64_t M[C::n];
+        uint32_t th[C::n];
+        class_masks<R>(r, thr, M, th);
+        compare_levels<R>(G, g, t, r.s, M, th, q_split, 16, acc, und);
+        acc |= und;  // equal on all 32 bits: r == thr, accepted
+        if (acc) S[r.s] = r.w ^ acc;
+    }
+}
+
+__device__ __forceinline__ void sweep_block_any(const GroupDev& G, uint32_t g, uint32_t colour,
+                                                uint32_t t, uint32_t idx, bool valid,
+                                                uint32_t q_split, SweepQueue& Q) {
+    switch (__builtin_amdgcn_readfirstlane(G.thr[g * kThrStride + 15])) {  // slot g's regime
+        case 0: sweep_block<0>(G, g, colour, t, idx, valid, q_split, Q); break;
+        case 1: sweep_block<1>(G, g, colour, t, idx, valid, q_split, Q); break;
+        case 2: sweep_block<2>(G, g, colour, t, idx, valid, q_split, Q); break;
+        default: sweep_block<3>(G, g, colour, t, idx, valid, q_split, Q); break;
     }
 }
 
 __global__ void __launch_bounds__(kSweepBlock)
-k_half_sweep(const GroupDev G, uint32_t colour, const uint32_t* __restrict__ ctr, uint32_t t_add) {
+k_half_sweep(const GroupDev G, uint32_t colour, const uint32_t* __restrict__ ctr, uint32_t t_add,
+             uint32_t q_split) {
+    __shared__ SweepQueue Q;
     const uint32_t t = ctr[0] + t_add;
     const uint32_t g = blockIdx.y;
     const uint32_t idx = blockIdx.x * kSweepBlock + threadIdx.x;
-    if (idx < (G.V >> 1)) update_word_any(G, g, colour, t, idx);
+    sweep_block_any(G, g, colour, t, idx, idx < (G.V >> 1), q_split, Q);
 }
 
 __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ prefix,
@@ -212,15 +344,16 @@ __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ pref
 __global__ void __launch_bounds__(kSweepBlock)
 k_half_sweep_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
                      uint32_t n_groups, uint32_t colour, const uint32_t* __restrict__ ctr,
-                     uint32_t t_add) {
+                     uint32_t t_add, uint32_t q_split) {
+    __shared__ SweepQueue Q;
     const uint32_t t = ctr[0] + t_add;
     const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
-    const GroupDev G = groups[gi];
+    const GroupDev G = uniform_record(groups + gi);
     const uint32_t local = blockIdx.x - prefix[gi];
     const uint32_t nb = sweep_blocks_per_slot(G.V);
     const uint32_t g = local / nb;
     const uint32_t idx = (local - g * nb) * kSweepBlock + threadIdx.x;
-    if (idx < (G.V >> 1)) update_word_any(G, g, colour, t, idx);
+    sweep_block_any(G, g, colour, t, idx, idx < (G.V >> 1), q_split, Q);
 }
 
 // ---------------------------------------------------------------------------
@@ -304,7 +437,7 @@ __global__ void __launch_bounds__(kEnergyBlock)
 k_energy_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
                  uint32_t n_groups) {
     const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
-    const GroupDev G = groups[gi];
+    const GroupDev G = uniform_record(groups + gi);
     const uint32_t local = blockIdx.x - prefix[gi];
     const uint32_t nb = energy_blocks_per_slot(G.V);
     const uint32_t g = local / nb;
@@ -407,7 +540,7 @@ k_pt(const GroupDev G, const uint32_t* __restrict__ ctr, uint32_t p_add) {
 
 __global__ void __launch_bounds__(64)
 k_pt_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ ctr, uint32_t p_add) {
-    const GroupDev G = groups[blockIdx.x];
+    const GroupDev G = uniform_record(groups + blockIdx.x);
     pt_group(G, ctr[1] + p_add);
 }
 
@@ -452,7 +585,7 @@ __global__ void __launch_bounds__(kSwapBlock)
 k_swap_apply_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
                      uint32_t n_groups) {
     const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
-    const GroupDev G = groups[gi];
+    const GroupDev G = uniform_record(groups + gi);
     if (G.N < 2 || G.lastmask[G.N - 1] == 0) return;
     const uint32_t site = (blockIdx.x - prefix[gi]) * kSwapBlock + threadIdx.x;
     if (site < G.V) swap_site(G, site);
@@ -534,6 +667,7 @@ __global__ void k_philox(const uint32_t* in, uint32_t* out, uint32_t n) {
 }  // namespace
 
 // ------------------------------- launchers ---------------------------------
+
 hipError_t launch_init_couplings(const GroupDev& g, hipStream_t s) {
     const uint32_t n = 2 * g.L * g.L;
     hipLaunchKernelGGL(k_init_couplings, dim3((n + 63) / 64), dim3(64), 0, s, g);
@@ -548,9 +682,9 @@ hipError_t launch_init_state(const GroupDev& g, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_half_sweep(const GroupDev& g, uint32_t colour, const uint32_t* ctr,
-                             uint32_t t_add, hipStream_t s) {
+                             uint32_t t_add, uint32_t q_split, hipStream_t s) {
     hipLaunchKernelGGL(k_half_sweep, dim3(sweep_blocks_per_slot(g.V), g.N), dim3(kSweepBlock), 0, s,
-                       g, colour, ctr, t_add);
+                       g, colour, ctr, t_add, q_split);
     return hipGetLastError();
 }
 hipError_t launch_energy(const GroupDev& g, int32_t* cnt, hipStream_t s) {
@@ -578,10 +712,10 @@ hipError_t launch_philox(const uint32_t* in, uint32_t* out, uint32_t n, hipStrea
     return hipGetLastError();
 }
 hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,
-                                     uint32_t t_add, hipStream_t s) {
+                                     uint32_t t_add, uint32_t q_split, hipStream_t s) {
     if (plan.n_blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_half_sweep_batched, dim3(plan.n_blocks), dim3(kSweepBlock), 0, s,
-                       plan.groups, plan.prefix, plan.n_groups, colour, ctr, t_add);
+                       plan.groups, plan.prefix, plan.n_groups, colour, ctr, t_add, q_split);
     return hipGetLastError();
 }
 hipError_t launch_energy_batched(const BatchPlan& plan, hipStream_t s) {

@@ -51,7 +51,8 @@ class qsg_group_desc(C.Structure):
 
 
 class qsg_run_config(C.Structure):
-    _fields_ = [("pt_every", C.c_uint32), ("swaplog_cap", C.c_uint32)]
+    _fields_ = [("pt_every", C.c_uint32), ("swaplog_cap", C.c_uint32),
+                ("sweep_split", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 ROUNDTRIP_DTYPE = np.dtype([("state", "<u4"), ("t_last", "<u4"), ("count", "<u4"),
@@ -173,7 +174,7 @@ class Ensemble:
     """
 
     def __init__(self, groups: Sequence, pt_every: int = 10, swaplog_cap: int = 1024,
-                 swap_table_cap: int = 0, stream=None, device=None):
+                 swap_table_cap: int = 0, stream=None, device=None, sweep_split: int = 0):
         import torch  # device memory and streams only
         self._torch = torch
         L_ = lib()
@@ -183,7 +184,7 @@ class Ensemble:
         for i, g in enumerate(self.groups):
             self.descs[i] = make_desc(g.L, g.L_tau, g.beta, len(g.gammas), g.group_id,
                                       g.mc_seed, g.j_seeds, swap_table_cap)
-        self.cfg = qsg_run_config(int(pt_every), int(swaplog_cap))
+        self.cfg = qsg_run_config(int(pt_every), int(swaplog_cap), int(sweep_split), 0)
         nbytes = L_.qsg_workspace_bytes(self.descs, self.n, C.byref(self.cfg))
         if nbytes == 0:
             raise QSGError(QSG_E_INVALID, "invalid group description")

@@ -42,7 +42,7 @@ def _desc(**kw):
 
 def _ws_bytes(desc, pt_every=10, cap=128):
     arr = (qsg.qsg_group_desc * 1)(desc)
-    cfg = qsg.qsg_run_config(pt_every, cap)
+    cfg = qsg.qsg_run_config(pt_every, cap, 0, 0)
     return qsg.lib().qsg_workspace_bytes(arr, 1, C.byref(cfg))
 
 
@@ -56,7 +56,7 @@ def test_workspace_validation():
 
 def test_create_rejects_bad_workspace_without_touching_the_device():
     arr = (qsg.qsg_group_desc * 1)(_desc())
-    cfg = qsg.qsg_run_config(10, 16)
+    cfg = qsg.qsg_run_config(10, 16, 0, 0)
     out = C.c_void_p()
     rc = qsg.lib().qsg_create(arr, 1, C.byref(cfg), None, 0, None, C.byref(out))
     assert rc == qsg.QSG_E_INVALID and not out.value
