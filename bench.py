@@ -47,8 +47,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--samples", type=int, default=64)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
+                    help="c2 (default): 64 samples, L=16, L_tau=128; c1: one sample, L=8, "
+                         "L_tau=32; c3: 256 uneven samples; c4: L=24, L_tau=2048, 128 samples")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=150)
+    ap.add_argument("--cpu-sweeps", type=int, default=0,
+                    help="oracle sweeps for the CPU baseline (0: about 15 s of work)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     return ap.parse_args()
@@ -86,7 +90,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = W.c2_plain_large(n_samples=args.samples)
+    wl = W.c2_plain_large(n_samples=args.samples) if args.workload == "c2" else \
+        W.ALL[args.workload]()
     pe = wl.pt_every
     upd_per_sweep = wl.spin_updates_per_sweep()
     words_per_sweep = sum(g.words for g in wl.groups)
@@ -147,8 +152,7 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {
-            "workload": f"{len(wl.groups)} samples x 64 replicas, L=16, L_tau=128, beta=8, "
-                        f"32 Gammas geometric in [2,4], PT every {pe} sweeps",
+            "workload": describe(wl, args.workload),
             "step": f"{pe} sweeps + energy pass + PT step + exchange pass, all samples",
             "spin_updates_per_step": upd_per_sweep * pe,
         },
@@ -177,6 +181,18 @@ def main():
     del energies
 
 
+def describe(wl, name):
+    if name == "c2":
+        return (f"{len(wl.groups)} samples x 64 replicas, L=16, L_tau=128, beta=8, "
+                f"32 Gammas geometric in [2,4], PT every {wl.pt_every} sweeps")
+    if name == "c1":
+        return "1 sample x 64 replicas, L=8, L_tau=32, beta=4, 16 Gammas in [1.5,4.5]"
+    if name == "c3":
+        return ("256 uneven samples x 64 replicas, L in {8..24}, L_tau in {64,128,256}, "
+                "beta=L_tau/16, 24-48 Gammas in [2,4]")
+    return "2 groups x 64 samples, L=24, L_tau=2048, beta=128, 48 Gammas in [2.8,3.6]"
+
+
 def cpu_baseline(wl, n_sweeps):
     """The oracle, as it is, on a bounded sample: one sample of the workload
     for a few sweeps with the OpenMP slot split over the host's cores."""
@@ -184,6 +200,8 @@ def cpu_baseline(wl, n_sweeps):
     cores = len(os.sched_getaffinity(0))
     threads = min(cores, 32)
     g = wl.groups[0]
+    if n_sweeps <= 0:  # about 15 s at ~1.4 ns per spin-update on 16 cores
+        n_sweeps = max(1, int(round(1.1e10 / g.spin_updates_per_sweep)))
     og = chain.OracleGroup.from_workload_group(g, log_cap=8)
     print(f"[bench] cpu baseline: oracle, 1 sample, {n_sweeps} sweeps, {threads} threads",
           file=sys.stderr, flush=True)
@@ -193,8 +211,9 @@ def cpu_baseline(wl, n_sweeps):
     upd = n_sweeps * g.spin_updates_per_sweep
     return {"value": round(dt / upd * 1e12, 2), "unit": "ps/spin-update", "cores": threads,
             "kind": "oracle",
-            "sample": f"1 of {len(wl.groups)} samples (L=16, L_tau=128, 32 Gammas), "
-                      f"{n_sweeps} sweeps, no PT; {upd:.3e} spin-updates in {dt:.1f} s"}
+            "sample": f"1 of {len(wl.groups)} groups (L={g.L}, L_tau={g.L_tau}, "
+                      f"{len(g.gammas)} Gammas), {n_sweeps} sweeps, no PT; {upd:.3e} "
+                      f"spin-updates in {dt:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -98,6 +98,8 @@ typedef struct {
 #define QSG_BATCHED 1u  /* one launch per pass over every group                */
 #define QSG_GRAPH 2u    /* with QSG_BATCHED: replay a captured HIP graph       */
 #define QSG_NO_PT 4u    /* skip the PT steps that fall due                     */
+#define QSG_FUSED 8u    /* with QSG_BATCHED: the sweeps of a whole PT chunk in
+                           one launch, one block per slot (small slots from LDS) */
 
 /* qsg_measure selectors (one at a time) */
 #define QSG_M_ENERGY 1u    /* int32 [G][N][64][2]: (Bsp, Bt) recomputed now      */
@@ -109,6 +111,9 @@ typedef struct {
 #define QSG_M_SUMS 7u      /* int64 [G][N][192]: per PT step sums of pre-exchange
                               Bsp[64], Bt[64], q[32], q^2[32]                   */
 #define QSG_M_COUNTERS 8u  /* uint64 [2]: sweeps done, PT steps done            */
+#define QSG_M_HIST 9u      /* uint32 [G][N][1024]: per PT step and lane, histogram
+                              of unsatisfied time bonds u = (V - Bt)/2 before the
+                              exchanges, bin = u*1024/(V+1), V = L*L*L_tau     */
 
 typedef struct {
     uint32_t state; /* 0 never at slot 0, 1 heading up, 2 heading down */
@@ -175,6 +180,11 @@ qsg_status qsg_get_tables(qsg_ctx* ctx, uint32_t group, uint32_t* thr,
 qsg_status qsg_build_tables(double beta, uint32_t L_tau, uint32_t n_gamma,
                             const double* gamma, uint32_t cap, uint32_t* thr,
                             uint8_t* swap_equal, uint32_t* swap_len, uint32_t* swap_thr);
+
+/* Colour-pass schedule of one group (the autotuner's knob): Philox blocks
+ * every word goes through before the words still undecided are packed into
+ * fewer waves, 1..16 (16 = never).  Results do not depend on it. */
+qsg_status qsg_set_schedule(qsg_ctx* ctx, uint32_t group, uint32_t sweep_split);
 
 /* Wall-clock deadline checked between PT chunks of qsg_sweep (0: due now,
  * so the next qsg_sweep stops after its first chunk); < 0 clears it. */

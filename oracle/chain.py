@@ -112,7 +112,8 @@ class _State(C.Structure):
         ("rt_count", C.c_void_p), ("rt_sum", C.c_void_p), ("acc", C.c_void_p),
         ("swaplog", C.c_void_p), ("log_cap", C.c_uint64),
         ("sum_Bsp", C.c_void_p), ("sum_Bt", C.c_void_p), ("sum_q", C.c_void_p),
-        ("sum_q2", C.c_void_p), ("counters", C.c_void_p), ("slot_base", C.c_uint32),
+        ("sum_q2", C.c_void_p), ("counters", C.c_void_p), ("hist", C.c_void_p),
+        ("slot_base", C.c_uint32),
     ]
 
 
@@ -169,6 +170,7 @@ class OracleGroup:
         self.sum_q = np.zeros(N * 32, dtype=np.int64)
         self.sum_q2 = np.zeros(N * 32, dtype=np.int64)
         self.counters = np.zeros(2, dtype=np.uint64)
+        self.hist = np.zeros(N * 1024, dtype=np.uint32)
         self._st = _State(
             self.L, self.L_tau, N, self.group_id, self.mc_seed,
             _p(self.thr), _p(self.pt_equal), _p(self.sw_len), _p(self.sw_off),
@@ -176,7 +178,7 @@ class OracleGroup:
             _p(self.Bsp), _p(self.Bt), _p(self.walker), _p(self.rt_state),
             _p(self.rt_tlast), _p(self.rt_count), _p(self.rt_sum), _p(self.acc),
             _p(self.swaplog), self.log_cap, _p(self.sum_Bsp), _p(self.sum_Bt),
-            _p(self.sum_q), _p(self.sum_q2), _p(self.counters), self.slot_base)
+            _p(self.sum_q), _p(self.sum_q2), _p(self.counters), _p(self.hist), self.slot_base)
 
     @classmethod
     def from_workload_group(cls, grp, **kw):

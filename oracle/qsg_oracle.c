@@ -298,6 +298,8 @@ typedef struct {
     int64_t *sum_Bsp, *sum_Bt; /* [N][64] sums of pre-swap values per PT step */
     int64_t *sum_q, *sum_q2;   /* [N][32]                                   */
     uint64_t *counters;      /* [0] sweeps done t, [1] PT steps done p   */
+    uint32_t *hist;          /* [N][1024] histogram of u = (V - Bt)/2 at every PT
+                                step before the exchanges, bin = u*1024/(V+1) */
     uint32_t slot_base;      /* slot g of this state is slot g+slot_base of the
                                 full ladder (random-number counters only); lets a
                                 test follow a few slots of a large group between
@@ -326,6 +328,9 @@ static void pt_step(oracle_state *st, int *failed) {
                 *failed = 1;
             st->sum_Bsp[g * 64 + j] += bs[j];
             st->sum_Bt[g * 64 + j] += bt[j];
+            /* bt = V - 2u with u the number of unsatisfied time bonds */
+            int64_t u = ((int64_t)V - bt[j]) / 2;
+            st->hist[(size_t)g * 1024 + (size_t)(u * 1024 / ((int64_t)V + 1))] += 1;
         }
         for (int q = 0; q < 32; ++q) {
             st->sum_q[g * 32 + q] += qq[q];

@@ -43,12 +43,12 @@ struct Region {
 // Byte layout of one group inside the workspace.
 struct GroupLayout {
     Region spins, Jx, Jy, jseed, thr, sw_thr, sw_len, sw_eq, cnt, meas, E, walker, rt, acc,
-        swaplog, sums, lastmask;
+        swaplog, sums, lastmask, hist;
 };
 
 struct Layout {
     std::vector<GroupLayout> g;
-    Region groups_dev, prefix_sweep, prefix_energy, prefix_swap, counters;
+    Region groups_dev, prefix_sweep, prefix_energy, prefix_swap, prefix_slots, counters;
     size_t total = 0;
 };
 
@@ -95,6 +95,7 @@ bool make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config& cfg,
     L.prefix_sweep = take(sizeof(uint32_t) * (n + 1));
     L.prefix_energy = take(sizeof(uint32_t) * (n + 1));
     L.prefix_swap = take(sizeof(uint32_t) * (n + 1));
+    L.prefix_slots = take(sizeof(uint32_t) * (n + 1));
     for (uint32_t i = 0; i < n; ++i) {
         if (!valid_desc(d[i], why)) {
             if (why) *why = "group " + std::to_string(i) + ": " + *why;
@@ -121,6 +122,7 @@ bool make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config& cfg,
         g.swaplog = take((size_t)cfg.swaplog_cap * pairs * 8);
         g.sums = take(N * qsg::kSumStride * 8);
         g.lastmask = take(N * 8);
+        g.hist = take(N * qsg::kHistBins * 4);
         L.g.push_back(g);
     }
     L.total = off;
@@ -167,11 +169,12 @@ struct qsg_ctx {
     uint64_t t = 0, p = 0;            // host mirror of the device counters
     qsg::BatchPlan plan_sweep{}, plan_energy{}, plan_swap{};
     GroupDev* d_groups = nullptr;
-    hipGraphExec_t chunk_exec = nullptr;
-    hipGraph_t chunk_graph = nullptr;
+    qsg::BatchPlan plan_slots{};      // one block per slot (fused sweeps)
+    uint32_t fused_lds_words = 0;     // slots at most this big run from LDS
+    hipGraphExec_t chunk_exec[2] = {nullptr, nullptr};  // [fused]
+    hipGraph_t chunk_graph[2] = {nullptr, nullptr};
     bool failed = false;
     bool spins_ready = false;
-    uint32_t q_split = 4;  // see qsg_run_config.sweep_split
     bool has_deadline = false;
     double deadline = 0;  // steady-clock seconds
     std::string err;
@@ -226,18 +229,20 @@ qsg_status check_ready(qsg_ctx* c) {
 }
 
 void destroy_graph(qsg_ctx* c) {
-    if (c->chunk_exec) (void)hipGraphExecDestroy(c->chunk_exec);
-    if (c->chunk_graph) (void)hipGraphDestroy(c->chunk_graph);
-    c->chunk_exec = nullptr;
-    c->chunk_graph = nullptr;
+    for (int f = 0; f < 2; ++f) {
+        if (c->chunk_exec[f]) (void)hipGraphExecDestroy(c->chunk_exec[f]);
+        if (c->chunk_graph[f]) (void)hipGraphDestroy(c->chunk_graph[f]);
+        c->chunk_exec[f] = nullptr;
+        c->chunk_graph[f] = nullptr;
+    }
 }
 
 // ---------------------------------------------------------------- passes --
 qsg_status plain_sweep(qsg_ctx* c, uint32_t t_add) {
     for (const GroupDev& g : c->gd)
-        QSG_HIP(c, qsg::launch_half_sweep(g, 0, c->d_counters, t_add, c->q_split, c->stream));
+        QSG_HIP(c, qsg::launch_half_sweep(g, 0, c->d_counters, t_add, c->stream));
     for (const GroupDev& g : c->gd)
-        QSG_HIP(c, qsg::launch_half_sweep(g, 1, c->d_counters, t_add, c->q_split, c->stream));
+        QSG_HIP(c, qsg::launch_half_sweep(g, 1, c->d_counters, t_add, c->stream));
     return QSG_OK;
 }
 
@@ -252,8 +257,8 @@ qsg_status plain_pt(qsg_ctx* c, uint32_t p_add) {
 }
 
 qsg_status batched_sweep(qsg_ctx* c, hipStream_t s, uint32_t t_add) {
-    QSG_HIP(c, qsg::launch_half_sweep_batched(c->plan_sweep, 0, c->d_counters, t_add, c->q_split, s));
-    QSG_HIP(c, qsg::launch_half_sweep_batched(c->plan_sweep, 1, c->d_counters, t_add, c->q_split, s));
+    QSG_HIP(c, qsg::launch_half_sweep_batched(c->plan_sweep, 0, c->d_counters, t_add, s));
+    QSG_HIP(c, qsg::launch_half_sweep_batched(c->plan_sweep, 1, c->d_counters, t_add, s));
     return QSG_OK;
 }
 
@@ -270,17 +275,28 @@ bool any_pt(const qsg_ctx* c) {
     return false;
 }
 
-qsg_status build_chunk_graph(qsg_ctx* c) {
-    if (c->chunk_exec) return QSG_OK;
+// One whole PT chunk on stream s: pt_every sweeps (colour passes over all
+// groups, or one fused launch), the energy pass, the PT step, the exchange
+// pass and the counter advance.
+qsg_status enqueue_chunk(qsg_ctx* c, hipStream_t s, bool fused) {
+    const uint32_t pe = c->cfg.pt_every;
+    if (fused) {
+        QSG_HIP(c, qsg::launch_chunk_fused(c->plan_slots, c->d_counters, pe, c->fused_lds_words, s));
+    } else {
+        for (uint32_t i = 0; i < pe; ++i)
+            if (qsg_status st = batched_sweep(c, s, i)) return st;
+    }
+    if (qsg_status st = batched_pt(c, s, 0)) return st;
+    QSG_HIP(c, qsg::launch_advance(c->d_counters, pe, 1, s));
+    return QSG_OK;
+}
+
+qsg_status build_chunk_graph(qsg_ctx* c, bool fused) {
+    const int f = fused ? 1 : 0;
+    if (c->chunk_exec[f]) return QSG_OK;
     hipStream_t s = c->capture_stream;
     QSG_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    qsg_status st = QSG_OK;
-    for (uint32_t i = 0; i < c->cfg.pt_every && st == QSG_OK; ++i) st = batched_sweep(c, s, i);
-    if (st == QSG_OK) st = batched_pt(c, s, 0);
-    if (st == QSG_OK) {
-        hipError_t e = qsg::launch_advance(c->d_counters, c->cfg.pt_every, 1, s);
-        if (e != hipSuccess) st = fail(c, QSG_E_DEVICE, "advance launch: %s", hipGetErrorString(e));
-    }
+    qsg_status st = enqueue_chunk(c, s, fused);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (st != QSG_OK) {
@@ -288,8 +304,8 @@ qsg_status build_chunk_graph(qsg_ctx* c) {
         return st;
     }
     if (e != hipSuccess) return fail(c, QSG_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
-    c->chunk_graph = graph;
-    QSG_HIP(c, hipGraphInstantiate(&c->chunk_exec, graph, nullptr, nullptr, 0));
+    c->chunk_graph[f] = graph;
+    QSG_HIP(c, hipGraphInstantiate(&c->chunk_exec[f], graph, nullptr, nullptr, 0));
     return QSG_OK;
 }
 
@@ -305,7 +321,7 @@ void for_state_regions(const qsg_ctx* c, F f) {
     for (size_t i = 0; i < c->gd.size(); ++i) {
         const GroupLayout& gl = c->layout.g[i];
         for (const Region* r : {&gl.spins, &gl.E, &gl.walker, &gl.rt, &gl.acc, &gl.swaplog,
-                                &gl.sums, &gl.lastmask, &gl.cnt})
+                                &gl.sums, &gl.lastmask, &gl.cnt, &gl.hist})
             f(*r);
     }
 }
@@ -343,7 +359,6 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
     qsg_ctx* c = new qsg_ctx();
     c->desc.assign(groups, groups + n_groups);
     c->cfg = *cfg;
-    c->q_split = cfg->sweep_split ? (cfg->sweep_split > 16 ? 16 : cfg->sweep_split) : 4;
     c->layout = L;
     c->ws = static_cast<uint8_t*>(d_workspace);
     c->ws_bytes = ws_bytes;
@@ -354,7 +369,8 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
     c->d_groups = at<GroupDev>(c, L.groups_dev);
 
     std::vector<uint32_t> pre_sweep(n_groups + 1, 0), pre_energy(n_groups + 1, 0),
-        pre_swap(n_groups + 1, 0);
+        pre_swap(n_groups + 1, 0), pre_slots(n_groups + 1, 0);
+    uint32_t max_v = 0;
     for (uint32_t i = 0; i < n_groups; ++i) {
         const qsg_group_desc& d = groups[i];
         const GroupLayout& gl = L.g[i];
@@ -372,6 +388,7 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         g.div_row = qsg::make_divisor(d.L);
         g.sw_cap = swap_cap_of(d);
         g.log_cap = cfg->swaplog_cap;
+        g.q_split = cfg->sweep_split ? (cfg->sweep_split > 16 ? 16 : cfg->sweep_split) : 4;
         g.spins = at<uint64_t>(c, gl.spins);
         g.Jx = at<uint64_t>(c, gl.Jx);
         g.Jy = at<uint64_t>(c, gl.Jy);
@@ -389,15 +406,20 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         g.swaplog = at<uint64_t>(c, gl.swaplog);
         g.sums = at<int64_t>(c, gl.sums);
         g.lastmask = at<uint64_t>(c, gl.lastmask);
+        g.hist = at<uint32_t>(c, gl.hist);
         c->gd.push_back(g);
         pre_sweep[i + 1] = pre_sweep[i] + g.N * qsg::sweep_blocks_per_slot(g.V);
         pre_energy[i + 1] = pre_energy[i] + (g.N >= 2 ? g.N * qsg::energy_blocks_per_slot(g.V) : 0);
         pre_swap[i + 1] = pre_swap[i] + (g.N >= 2 ? qsg::swap_blocks(g.V) : 0);
+        pre_slots[i + 1] = pre_slots[i] + g.N;
+        if (g.V > max_v) max_v = g.V;
     }
     c->plan_sweep = {c->d_groups, at<uint32_t>(c, L.prefix_sweep), n_groups, pre_sweep[n_groups]};
     c->plan_energy = {c->d_groups, at<uint32_t>(c, L.prefix_energy), n_groups,
                       pre_energy[n_groups]};
     c->plan_swap = {c->d_groups, at<uint32_t>(c, L.prefix_swap), n_groups, pre_swap[n_groups]};
+    c->plan_slots = {c->d_groups, at<uint32_t>(c, L.prefix_slots), n_groups, pre_slots[n_groups]};
+    c->fused_lds_words = max_v <= qsg::kFusedLdsMaxWords ? max_v : 0;
 
     auto bail = [&](qsg_status st) {
         g_create_error = c->err;
@@ -422,6 +444,8 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
                               hipMemcpyHostToDevice, s));
     CREATE_HIP(hipMemcpyAsync(const_cast<uint32_t*>(c->plan_swap.prefix), pre_swap.data(), 4 * (n_groups + 1),
                               hipMemcpyHostToDevice, s));
+    CREATE_HIP(hipMemcpyAsync(const_cast<uint32_t*>(c->plan_slots.prefix), pre_slots.data(),
+                              4 * (n_groups + 1), hipMemcpyHostToDevice, s));
     const uint32_t zero2[2] = {0, 0};
     CREATE_HIP(hipMemcpyAsync(c->d_counters, zero2, sizeof zero2, hipMemcpyHostToDevice, s));
     for (uint32_t i = 0; i < n_groups; ++i) {
@@ -484,21 +508,27 @@ qsg_status qsg_init_spins(qsg_ctx* c) {
 
 qsg_status qsg_sweep(qsg_ctx* c, uint32_t n_sweeps, uint32_t flags) {
     if (qsg_status st = check_ctx(c)) return st;
-    if (flags & ~(QSG_BATCHED | QSG_GRAPH | QSG_NO_PT))
+    if (flags & ~(QSG_BATCHED | QSG_GRAPH | QSG_NO_PT | QSG_FUSED))
         return fail(c, QSG_E_INVALID, "unknown flags 0x%x", flags);
-    if ((flags & QSG_GRAPH) && !(flags & QSG_BATCHED))
-        return fail(c, QSG_E_INVALID, "QSG_GRAPH needs QSG_BATCHED");
+    if ((flags & (QSG_GRAPH | QSG_FUSED)) && !(flags & QSG_BATCHED))
+        return fail(c, QSG_E_INVALID, "QSG_GRAPH and QSG_FUSED need QSG_BATCHED");
     if (qsg_status st = check_ready(c)) return st;
     const bool batched = flags & QSG_BATCHED;
     const bool do_pt = !(flags & QSG_NO_PT) && c->cfg.pt_every > 0 && any_pt(c);
     const uint32_t pe = c->cfg.pt_every;
     uint32_t done = 0;
     while (done < n_sweeps) {
-        // whole PT chunks aligned to the cadence can replay the graph
-        if (batched && (flags & QSG_GRAPH) && do_pt && pe > 0 && c->t % pe == 0 &&
+        // whole PT chunks aligned to the cadence: one fused launch for the
+        // sweeps and/or a replay of the captured chunk graph
+        const bool fused = flags & QSG_FUSED;
+        if (batched && (flags & (QSG_GRAPH | QSG_FUSED)) && do_pt && pe > 0 && c->t % pe == 0 &&
             n_sweeps - done >= pe) {
-            if (qsg_status st = build_chunk_graph(c)) return st;
-            QSG_HIP(c, hipGraphLaunch(c->chunk_exec, c->stream));
+            if (flags & QSG_GRAPH) {
+                if (qsg_status st = build_chunk_graph(c, fused)) return st;
+                QSG_HIP(c, hipGraphLaunch(c->chunk_exec[fused ? 1 : 0], c->stream));
+            } else if (qsg_status st = enqueue_chunk(c, c->stream, fused)) {
+                return st;
+            }
             done += pe;
             c->t += pe;
             c->p += 1;
@@ -560,6 +590,7 @@ qsg_status qsg_measure(qsg_ctx* c, uint32_t what, void* host_out, size_t bytes) 
             case QSG_M_SWAPLOG: need += (size_t)c->cfg.swaplog_cap * pairs * 8; break;
             case QSG_M_ROUNDTRIP: need += N * 64 * sizeof(qsg_roundtrip); break;
             case QSG_M_SUMS: need += N * qsg::kSumStride * 8; break;
+            case QSG_M_HIST: need += N * qsg::kHistBins * 4; break;
             case QSG_M_COUNTERS: need = 16; break;
             default: return fail(c, QSG_E_INVALID, "unknown measurement %u", what);
         }
@@ -630,6 +661,10 @@ qsg_status qsg_measure(qsg_ctx* c, uint32_t what, void* host_out, size_t bytes) 
             case QSG_M_SUMS:
                 QSG_HIP(c, hipMemcpy(o, g.sums, N * qsg::kSumStride * 8, hipMemcpyDeviceToHost));
                 o += N * qsg::kSumStride * 8;
+                break;
+            case QSG_M_HIST:
+                QSG_HIP(c, hipMemcpy(o, g.hist, N * qsg::kHistBins * 4, hipMemcpyDeviceToHost));
+                o += N * qsg::kHistBins * 4;
                 break;
         }
     }
@@ -771,6 +806,21 @@ qsg_status qsg_build_tables(double beta, uint32_t L_tau, uint32_t n_gamma, const
                                    swap_thr, err, sizeof err);
     if (rc == -1) return fail(nullptr, QSG_E_INVALID, "%s", err);
     if (rc != 0) return fail(nullptr, QSG_E_UNSUPPORTED, "%s", err);
+    return QSG_OK;
+}
+
+qsg_status qsg_set_schedule(qsg_ctx* c, uint32_t group, uint32_t sweep_split) {
+    if (qsg_status st = check_ctx(c)) return st;
+    if (group >= c->gd.size()) return fail(c, QSG_E_INVALID, "group %u out of range", group);
+    if (sweep_split < 1 || sweep_split > 16)
+        return fail(c, QSG_E_INVALID, "sweep_split %u outside 1..16", sweep_split);
+    GroupDev& g = c->gd[group];
+    g.q_split = sweep_split;
+    // later launches (and the next graph capture) see the new record
+    QSG_HIP(c, hipMemcpyAsync(c->d_groups + group, &g, sizeof(GroupDev), hipMemcpyHostToDevice,
+                              c->stream));
+    QSG_HIP(c, hipStreamSynchronize(c->stream));
+    destroy_graph(c);
     return QSG_OK;
 }
 

@@ -24,6 +24,9 @@ constexpr int kCntStride = 64 + 64 + 32;  // int32 per slot
 constexpr int kSumStride = 192;
 // Thresholds per slot, padded.
 constexpr int kThrStride = 16;
+// Histogram of the unsatisfied time bonds u = (V - Bt)/2 per slot, taken at
+// every PT step before the exchanges: bin = u * kHistBins / (V + 1).
+constexpr int kHistBins = 1024;
 
 // Exact division by a fixed d for x < 2^31: q = mulhi(x, m) >> s, or
 // x >> s when m == 0 (d a power of two).
@@ -54,7 +57,7 @@ struct GroupDev {
     uint32_t V;           // words per slot = L*L*Ltau
     uint32_t sw_cap;      // entries per exchange table
     uint32_t log_cap;     // rows of the swap log
-    uint32_t pad0;
+    uint32_t q_split;     // colour-pass schedule: Philox blocks before packing
     Divisor div_half_plane, div_half_row, div_plane, div_row;
     uint64_t* spins;          // [N][Ltau][L][L]
     uint64_t* Jx;             // [L*L]
@@ -73,6 +76,7 @@ struct GroupDev {
     int64_t* sums;            // [N][kSumStride]
     uint64_t* lastmask;       // [N] masks of the latest PT step (+ any flag at [N-1])
     int32_t* meas;            // [N][kCntStride] scratch for on-demand measurement
+    uint32_t* hist;           // [N][kHistBins]
 };
 
 // Launchers (qsg_kernels.hip).  All enqueue on `s` and return the launch
@@ -81,11 +85,11 @@ struct GroupDev {
 hipError_t launch_init_couplings(const GroupDev& g, hipStream_t s);
 hipError_t launch_init_spins(const GroupDev& g, hipStream_t s);
 hipError_t launch_init_state(const GroupDev& g, hipStream_t s);
-// q_split: Philox blocks every word of a colour pass goes through before the
-// words still undecided are packed into the first waves of the block
-// (16: no packing).  Results do not depend on it.
+// The colour pass follows the group's schedule G.q_split: Philox blocks every
+// word goes through before the words still undecided are packed into the
+// first waves of the block (16: no packing).  Results do not depend on it.
 hipError_t launch_half_sweep(const GroupDev& g, uint32_t colour, const uint32_t* ctr,
-                             uint32_t t_add, uint32_t q_split, hipStream_t s);
+                             uint32_t t_add, hipStream_t s);
 hipError_t launch_energy(const GroupDev& g, int32_t* cnt, hipStream_t s);
 hipError_t launch_pt(const GroupDev& g, const uint32_t* ctr, uint32_t p_add, hipStream_t s);
 hipError_t launch_advance(uint32_t* ctr, uint32_t dt, uint32_t dp, hipStream_t s);
@@ -104,8 +108,14 @@ struct BatchPlan {
     uint32_t n_blocks;
 };
 hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,
-                                     uint32_t t_add, uint32_t q_split, hipStream_t s);
+                                     uint32_t t_add, hipStream_t s);
 hipError_t launch_energy_batched(const BatchPlan& plan, hipStream_t s);
+// Fused sweeps over every slot (one block per slot, `slots.prefix` counts
+// slots per group): n_sweeps sweeps in one launch; slots of at most
+// lds_words words run from LDS.
+hipError_t launch_chunk_fused(const BatchPlan& slots, const uint32_t* ctr, uint32_t n_sweeps,
+                              uint32_t lds_words, hipStream_t s);
+constexpr uint32_t kFusedLdsMaxWords = 7168;  // 56 KiB of spins per block
 hipError_t launch_pt_batched(const GroupDev* groups, uint32_t n_groups, const uint32_t* ctr,
                              uint32_t p_add, hipStream_t s);
 hipError_t launch_swap_apply_batched(const BatchPlan& plan, hipStream_t s);
@@ -116,7 +126,7 @@ __host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V);
 __host__ __device__ inline uint32_t swap_blocks(uint32_t V);
 
 constexpr int kSweepBlock = 256;   // threads per block of a colour pass
-constexpr int kEnergyWords = 16;   // words per thread in the energy pass
+constexpr int kEnergyWords = 32;   // words per thread in the energy pass
 constexpr int kEnergyBlock = 256;
 constexpr int kSwapBlock = 256;
 

@@ -251,11 +251,10 @@ __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, ui
 // tail of levels).  Every thread of the block calls this (it synchronises);
 // `valid` is false for threads past the last word.
 template <int R>
-__device__ __forceinline__ void sweep_block(const GroupDev& G, uint32_t g, uint32_t colour,
-                                            uint32_t t, uint32_t idx, bool valid,
+__device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
+                                            uint32_t colour, uint32_t t, uint32_t idx, bool valid,
                                             uint32_t q_split, SweepQueue& Q) {
     using C = Classes<R>;
-    uint64_t* __restrict__ S = G.spins + (size_t)g * G.V;
     const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
     if (threadIdx.x == 0) Q.count = 0;
     __syncthreads();
@@ -310,25 +309,37 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint32_t g, uint3
     }
 }
 
-__device__ __forceinline__ void sweep_block_any(const GroupDev& G, uint32_t g, uint32_t colour,
-                                                uint32_t t, uint32_t idx, bool valid,
-                                                uint32_t q_split, SweepQueue& Q) {
+// S: the slot's spins (global memory, or a copy in LDS).
+__device__ __forceinline__ void sweep_block_any(const GroupDev& G, uint64_t* S, uint32_t g,
+                                                uint32_t colour, uint32_t t, uint32_t idx,
+                                                bool valid, uint32_t q_split, SweepQueue& Q) {
     switch (__builtin_amdgcn_readfirstlane(G.thr[g * kThrStride + 15])) {  // slot g's regime
-        case 0: sweep_block<0>(G, g, colour, t, idx, valid, q_split, Q); break;
-        case 1: sweep_block<1>(G, g, colour, t, idx, valid, q_split, Q); break;
-        case 2: sweep_block<2>(G, g, colour, t, idx, valid, q_split, Q); break;
-        default: sweep_block<3>(G, g, colour, t, idx, valid, q_split, Q); break;
+        case 0: sweep_block<0>(G, S, g, colour, t, idx, valid, q_split, Q); break;
+        case 1: sweep_block<1>(G, S, g, colour, t, idx, valid, q_split, Q); break;
+        case 2: sweep_block<2>(G, S, g, colour, t, idx, valid, q_split, Q); break;
+        default: sweep_block<3>(G, S, g, colour, t, idx, valid, q_split, Q); break;
     }
 }
 
+// Blocks are dealt to the eight XCDs round-robin (block b runs on XCD b % 8).
+// Renumber them so that every XCD receives one contiguous run of logical
+// blocks: neighbouring tau-planes then meet in the same L2.  A bijection of
+// [0, n); only the speed depends on the dispatch order.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
+    constexpr uint32_t kXcd = 8;
+    const uint32_t q = n / kXcd, r = n % kXcd;
+    const uint32_t x = b % kXcd, i = b / kXcd;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 __global__ void __launch_bounds__(kSweepBlock)
-k_half_sweep(const GroupDev G, uint32_t colour, const uint32_t* __restrict__ ctr, uint32_t t_add,
-             uint32_t q_split) {
+k_half_sweep(const GroupDev G, uint32_t colour, const uint32_t* __restrict__ ctr, uint32_t t_add) {
     __shared__ SweepQueue Q;
     const uint32_t t = ctr[0] + t_add;
-    const uint32_t g = blockIdx.y;
-    const uint32_t idx = blockIdx.x * kSweepBlock + threadIdx.x;
-    sweep_block_any(G, g, colour, t, idx, idx < (G.V >> 1), q_split, Q);
+    const uint32_t b = xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const uint32_t g = b / gridDim.x;
+    const uint32_t idx = (b - g * gridDim.x) * kSweepBlock + threadIdx.x;
+    sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q);
 }
 
 __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ prefix,
@@ -344,16 +355,54 @@ __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ pref
 __global__ void __launch_bounds__(kSweepBlock)
 k_half_sweep_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
                      uint32_t n_groups, uint32_t colour, const uint32_t* __restrict__ ctr,
-                     uint32_t t_add, uint32_t q_split) {
+                     uint32_t t_add) {
     __shared__ SweepQueue Q;
     const uint32_t t = ctr[0] + t_add;
-    const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
+    const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+    const uint32_t gi = find_group(prefix, n_groups, b);
     const GroupDev G = uniform_record(groups + gi);
-    const uint32_t local = blockIdx.x - prefix[gi];
+    const uint32_t local = b - prefix[gi];
     const uint32_t nb = sweep_blocks_per_slot(G.V);
     const uint32_t g = local / nb;
     const uint32_t idx = (local - g * nb) * kSweepBlock + threadIdx.x;
-    sweep_block_any(G, g, colour, t, idx, idx < (G.V >> 1), q_split, Q);
+    sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q);
+}
+
+// ---------------------------------------------------------------------------
+// Fused sweeps: one block owns one slot for `n_sweeps` sweeps (no other
+// block touches it before the PT step), so colour passes are separated by
+// block barriers only and all sweeps of a PT chunk are one launch.  Slots of
+// at most `lds_words` words are copied into LDS for the chunk.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kSweepBlock)
+k_chunk_fused(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ slot_prefix,
+              uint32_t n_groups, const uint32_t* __restrict__ ctr, uint32_t n_sweeps,
+              uint32_t lds_words) {
+    extern __shared__ uint64_t lds_spins[];
+    __shared__ SweepQueue Q;
+    const uint32_t gi = find_group(slot_prefix, n_groups, blockIdx.x);
+    const GroupDev G = uniform_record(groups + gi);
+    const uint32_t g = blockIdx.x - slot_prefix[gi];
+    const uint32_t V = G.V, half = V >> 1;
+    uint64_t* Sg = G.spins + (size_t)g * V;
+    const bool in_lds = V <= lds_words;
+    uint64_t* S = in_lds ? lds_spins : Sg;
+    if (in_lds) {
+        for (uint32_t i = threadIdx.x; i < V; i += kSweepBlock) lds_spins[i] = Sg[i];
+        __syncthreads();
+    }
+    const uint32_t t0 = ctr[0];
+    for (uint32_t it = 0; it < n_sweeps; ++it) {
+        for (uint32_t colour = 0; colour < 2; ++colour) {
+            for (uint32_t base = 0; base < half; base += kSweepBlock) {
+                const uint32_t idx = base + threadIdx.x;
+                sweep_block_any(G, S, g, colour, t0 + it, idx, idx < half, G.q_split, Q);
+            }
+            __syncthreads();  // the next colour reads what this one wrote
+        }
+    }
+    if (in_lds)
+        for (uint32_t i = threadIdx.x; i < V; i += kSweepBlock) Sg[i] = lds_spins[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -364,50 +413,90 @@ k_half_sweep_batched(const GroupDev* __restrict__ groups, const uint32_t* __rest
 // then turns counters into per-lane totals with ballots and adds them to
 // the slot's counters with integer atomics (order-independent, exact).
 // ---------------------------------------------------------------------------
-template <int NB>
-__device__ __forceinline__ void vadd(uint64_t (&C)[NB], uint64_t x) {
+// Bit-sliced per-lane counter: value = ones + 2 twos + 4 fours + 8 * (hi as
+// a binary number).  Planes are added eight at a time with carry-save adders
+// (Harley-Seal), so each added plane costs about two bitop3 per 32 lanes.
+template <int NH>
+struct LaneCounter {
+    uint64_t ones = 0, twos = 0, fours = 0;
+    uint64_t hi[NH] = {};
+};
+
+// carry-save adder: (h, l) with a + b + c = 2h + l per lane
+__device__ __forceinline__ void csa(uint64_t& h, uint64_t& l, uint64_t a, uint64_t b, uint64_t c) {
+    const uint32_t alo = (uint32_t)a, blo = (uint32_t)b, clo = (uint32_t)c;
+    const uint32_t ahi = (uint32_t)(a >> 32), bhi = (uint32_t)(b >> 32), chi = (uint32_t)(c >> 32);
+    l = lo_hi(__builtin_amdgcn_bitop3_b32(alo, blo, clo, 0x96),
+              __builtin_amdgcn_bitop3_b32(ahi, bhi, chi, 0x96));  // a ^ b ^ c
+    h = lo_hi(__builtin_amdgcn_bitop3_b32(alo, blo, clo, 0xE8),
+              __builtin_amdgcn_bitop3_b32(ahi, bhi, chi, 0xE8));  // majority
+}
+
+template <int NH>
+__device__ __forceinline__ void add8(LaneCounter<NH>& c, const uint64_t (&x)[8]) {
+    uint64_t twosA, twosB, foursA, foursB, eights;
+    csa(twosA, c.ones, c.ones, x[0], x[1]);
+    csa(twosB, c.ones, c.ones, x[2], x[3]);
+    csa(foursA, c.twos, c.twos, twosA, twosB);
+    csa(twosA, c.ones, c.ones, x[4], x[5]);
+    csa(twosB, c.ones, c.ones, x[6], x[7]);
+    csa(foursB, c.twos, c.twos, twosA, twosB);
+    csa(eights, c.fours, c.fours, foursA, foursB);
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const uint64_t carry = C[i] & x;
-        C[i] ^= x;
-        x = carry;
+    for (int i = 0; i < NH; ++i) {  // ripple the eights into the binary part
+        const uint64_t carry = c.hi[i] & eights;
+        c.hi[i] ^= eights;
+        eights = carry;
     }
 }
 
-template <int NB>
-__device__ __forceinline__ uint32_t lane_total(const uint64_t (&C)[NB], uint32_t j) {
-    uint32_t tot = 0;
+// Total of lane j over the wave (all 64 threads' counters), via ballots.
+template <int NH>
+__device__ __forceinline__ uint32_t lane_total(const LaneCounter<NH>& c, uint32_t j) {
+    uint32_t tot = (uint32_t)__popcll(__ballot((int)((c.ones >> j) & 1u))) +
+                   ((uint32_t)__popcll(__ballot((int)((c.twos >> j) & 1u))) << 1) +
+                   ((uint32_t)__popcll(__ballot((int)((c.fours >> j) & 1u))) << 2);
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
-        tot += (uint32_t)__popcll(__ballot((int)((C[i] >> j) & 1u))) << i;
+    for (int i = 0; i < NH; ++i)
+        tot += (uint32_t)__popcll(__ballot((int)((c.hi[i] >> j) & 1u))) << (3 + i);
     return tot;
 }
 
 __device__ __forceinline__ void energy_block(const GroupDev& G, uint32_t g, uint32_t blk,
                                              int32_t* __restrict__ cnt) {
+    static_assert(kEnergyWords % 8 == 0, "words come in chunks of eight");
     const uint32_t L = G.L, P = L * L, V = G.V;
     const uint64_t* __restrict__ S = G.spins + (size_t)g * V;
-    uint64_t Csp[6] = {0, 0, 0, 0, 0, 0};  // <= 2*kEnergyWords = 32
-    uint64_t Ct[5] = {0, 0, 0, 0, 0};
-    uint64_t Cq[5] = {0, 0, 0, 0, 0};
+    // per thread at most 2*kEnergyWords = 64 unsatisfied space bonds per lane
+    LaneCounter<4> Csp;
+    LaneCounter<3> Ct, Cq;
     const uint32_t first = blk * (kEnergyBlock * kEnergyWords) + threadIdx.x;
-#pragma unroll 4
-    for (int k = 0; k < kEnergyWords; ++k) {
-        const uint32_t s = first + (uint32_t)k * kEnergyBlock;
-        if (s < V) {
-            const uint32_t tau = fast_div(s, G.div_plane);
-            const uint32_t rem = s - tau * P;
-            const uint32_t y = fast_div(rem, G.div_row);
-            const uint32_t x = rem - y * L;
-            const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-            const uint32_t yp = (y + 1 == L) ? 0 : y + 1;
-            const uint32_t tp = (tau + 1 == G.Ltau) ? 0 : tau + 1;
-            const uint64_t w = S[s];
-            vadd(Csp, w ^ S[tau * P + y * L + xp] ^ G.Jx[rem]);
-            vadd(Csp, w ^ S[tau * P + yp * L + x] ^ G.Jy[rem]);
-            vadd(Ct, w ^ S[tp * P + rem]);
-            vadd(Cq, (w ^ (w >> 1)) & 0x5555555555555555ull);
+#pragma unroll 1
+    for (int k0 = 0; k0 < kEnergyWords; k0 += 8) {
+        uint64_t xs[8], ys[8], ts[8], qs[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t s = first + (uint32_t)(k0 + k) * kEnergyBlock;
+            xs[k] = ys[k] = ts[k] = qs[k] = 0;
+            if (s < V) {
+                const uint32_t tau = fast_div(s, G.div_plane);
+                const uint32_t rem = s - tau * P;
+                const uint32_t y = fast_div(rem, G.div_row);
+                const uint32_t x = rem - y * L;
+                const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+                const uint32_t yp = (y + 1 == L) ? 0 : y + 1;
+                const uint32_t tp = (tau + 1 == G.Ltau) ? 0 : tau + 1;
+                const uint64_t w = S[s];
+                xs[k] = w ^ S[tau * P + y * L + xp] ^ G.Jx[rem];  // +x bond unsatisfied
+                ys[k] = w ^ S[tau * P + yp * L + x] ^ G.Jy[rem];  // +y bond unsatisfied
+                ts[k] = w ^ S[tp * P + rem];                        // +tau bond unsatisfied
+                qs[k] = (w ^ (w >> 1)) & 0x5555555555555555ull;     // pair (2p, 2p+1) differs
+            }
         }
+        add8(Csp, xs);
+        add8(Csp, ys);
+        add8(Ct, ts);
+        add8(Cq, qs);
     }
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t my_sp = 0, my_t = 0, my_q = 0;
@@ -466,6 +555,8 @@ __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
         int64_t* sm = G.sums + (size_t)g * kSumStride;
         sm[j] += bsp;
         sm[64 + j] += bt;
+        const uint32_t u = (uint32_t)(V - bt) >> 1;
+        atomicAdd(&G.hist[g * kHistBins + (uint32_t)(((uint64_t)u * kHistBins) / ((uint64_t)V + 1))], 1u);
         if (j < 32) {
             const int64_t q = (int64_t)V - 2 * (int64_t)c[128 + j];
             c[128 + j] = 0;
@@ -636,6 +727,7 @@ __global__ void k_init_state(const GroupDev G) {
         G.rt[g * 64 + j] = r;
         for (int k = j; k < kCntStride; k += 64) G.cnt[g * kCntStride + k] = 0;
         for (int k = j; k < kSumStride; k += 64) G.sums[(size_t)g * kSumStride + k] = 0;
+        for (int k = j; k < kHistBins; k += 64) G.hist[(size_t)g * kHistBins + k] = 0;
         G.E[(g * 64 + j) * 2 + 0] = 0;
         G.E[(g * 64 + j) * 2 + 1] = 0;
     }
@@ -682,9 +774,9 @@ hipError_t launch_init_state(const GroupDev& g, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_half_sweep(const GroupDev& g, uint32_t colour, const uint32_t* ctr,
-                             uint32_t t_add, uint32_t q_split, hipStream_t s) {
+                             uint32_t t_add, hipStream_t s) {
     hipLaunchKernelGGL(k_half_sweep, dim3(sweep_blocks_per_slot(g.V), g.N), dim3(kSweepBlock), 0, s,
-                       g, colour, ctr, t_add, q_split);
+                       g, colour, ctr, t_add);
     return hipGetLastError();
 }
 hipError_t launch_energy(const GroupDev& g, int32_t* cnt, hipStream_t s) {
@@ -712,12 +804,26 @@ hipError_t launch_philox(const uint32_t* in, uint32_t* out, uint32_t n, hipStrea
     return hipGetLastError();
 }
 hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,
-                                     uint32_t t_add, uint32_t q_split, hipStream_t s) {
+                                     uint32_t t_add, hipStream_t s) {
     if (plan.n_blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_half_sweep_batched, dim3(plan.n_blocks), dim3(kSweepBlock), 0, s,
-                       plan.groups, plan.prefix, plan.n_groups, colour, ctr, t_add, q_split);
+                       plan.groups, plan.prefix, plan.n_groups, colour, ctr, t_add);
     return hipGetLastError();
 }
+hipError_t launch_chunk_fused(const BatchPlan& slots, const uint32_t* ctr, uint32_t n_sweeps,
+                              uint32_t lds_words, hipStream_t s) {
+    if (slots.n_blocks == 0) return hipSuccess;
+    const size_t lds = (size_t)lds_words * sizeof(uint64_t);
+    if (lds > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_chunk_fused,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_chunk_fused, dim3(slots.n_blocks), dim3(kSweepBlock), lds, s, slots.groups,
+                       slots.prefix, slots.n_groups, ctr, n_sweeps, lds_words);
+    return hipGetLastError();
+}
+
 hipError_t launch_energy_batched(const BatchPlan& plan, hipStream_t s) {
     if (plan.n_blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_energy_batched, dim3(plan.n_blocks), dim3(kEnergyBlock), 0, s,

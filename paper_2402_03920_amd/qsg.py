@@ -30,6 +30,7 @@ QSG_PLAIN = 0
 QSG_BATCHED = 1
 QSG_GRAPH = 2
 QSG_NO_PT = 4
+QSG_FUSED = 8
 
 QSG_M_ENERGY = 1
 QSG_M_OVERLAP = 2
@@ -39,6 +40,8 @@ QSG_M_SWAPLOG = 5
 QSG_M_ROUNDTRIP = 6
 QSG_M_SUMS = 7
 QSG_M_COUNTERS = 8
+QSG_M_HIST = 9
+HIST_BINS = 1024
 
 SUM_STRIDE = 192
 
@@ -88,6 +91,7 @@ _SIGS = {
                                      C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p]),
     "qsg_set_deadline": (C.c_int32, [C.c_void_p, C.c_double]),
+    "qsg_set_schedule": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32]),
     "qsg_sync": (C.c_int32, [C.c_void_p]),
     "qsg_last_error": (C.c_char_p, [C.c_void_p]),
     "qsg_destroy": (None, [C.c_void_p]),
@@ -240,6 +244,9 @@ class Ensemble:
     def sync(self):
         _check(lib().qsg_sync(self.ctx), self.ctx)
 
+    def set_schedule(self, i: int, sweep_split: int):
+        _check(lib().qsg_set_schedule(self.ctx, int(i), int(sweep_split)), self.ctx)
+
     def set_deadline(self, seconds: float):
         _check(lib().qsg_set_deadline(self.ctx, float(seconds)), self.ctx)
 
@@ -301,6 +308,11 @@ class Ensemble:
         tot = sum(len(g.gammas) * SUM_STRIDE for g in self.groups)
         flat = self._measure(QSG_M_SUMS, np.int64, tot)
         return self._split(flat, lambda N: (N * SUM_STRIDE, (N, SUM_STRIDE)))
+
+    def histograms(self) -> List[np.ndarray]:
+        tot = sum(len(g.gammas) * HIST_BINS for g in self.groups)
+        flat = self._measure(QSG_M_HIST, np.uint32, tot)
+        return self._split(flat, lambda N: (N * HIST_BINS, (N, HIST_BINS)))
 
     def counters(self):
         v = self._measure(QSG_M_COUNTERS, np.uint64, 2)

@@ -19,6 +19,7 @@ def compare_state(ens, ogs, check_sums=True):
     rts = ens.roundtrips()
     logs = ens.swaplog_rows()
     sums = ens.sums() if check_sums else None
+    hists = ens.histograms() if check_sums else None
     t, p = ens.counters()
     for i, og in enumerate(ogs):
         assert (t, p) == (og.t, og.p), (i, t, p, og.t, og.p)
@@ -46,4 +47,5 @@ def compare_state(ens, ogs, check_sums=True):
             assert np.array_equal(s[:, 64:128], og.sum_Bt.reshape(N, 64)), f"group {i}: sum Bt"
             assert np.array_equal(s[:, 128:160], og.sum_q.reshape(N, 32)), f"group {i}: sum q"
             assert np.array_equal(s[:, 160:192], og.sum_q2.reshape(N, 32)), f"group {i}: sum q2"
+            assert np.array_equal(hists[i], og.hist.reshape(N, 1024)), f"group {i}: Bt histogram"
     return words

@@ -24,7 +24,9 @@ if not torch.cuda.is_available():  # collected on CPU-only hosts, never run ther
 from paper_2402_03920_amd import qsg  # noqa: E402
 
 MODES = {"plain": qsg.QSG_PLAIN, "batched": qsg.QSG_BATCHED,
-         "graph": qsg.QSG_BATCHED | qsg.QSG_GRAPH}
+         "graph": qsg.QSG_BATCHED | qsg.QSG_GRAPH,
+         "fused": qsg.QSG_BATCHED | qsg.QSG_FUSED,
+         "fused_graph": qsg.QSG_BATCHED | qsg.QSG_FUSED | qsg.QSG_GRAPH}
 
 
 def say(*a):
@@ -113,7 +115,7 @@ def test_c1_plain_full_bit_exact():
     say("[parity] c1 oracle 1000 sweeps")
     og = chain.OracleGroup.from_workload_group(wl.groups[0], log_cap=128)
     og.run(wl.sweeps, wl.pt_every, threads=16)
-    for mode in ("plain", "graph"):
+    for mode in ("plain", "graph", "fused_graph"):
         say(f"[parity] c1 gpu mode={mode}")
         with qsg.Ensemble(wl.groups, pt_every=wl.pt_every, swaplog_cap=128) as ens:
             ens.init_spins()
@@ -181,8 +183,25 @@ def test_modes_agree_on_uneven_ensemble():
             ens.init_spins()
             ens.sweep(30, MODES[mode])
             states[mode] = ens.get_state()
-    assert np.array_equal(states["plain"], states["batched"])
-    assert np.array_equal(states["plain"], states["graph"])
+    for mode in MODES:
+        assert np.array_equal(states["plain"], states[mode]), mode
+
+
+@pytest.mark.parametrize("split", [1, 2, 3, 5, 8, 16])
+def test_every_schedule_gives_the_same_trajectory(split):
+    """The colour-pass schedule (when undecided words are packed) only moves
+    work between waves: the trajectory is identical for every value, per
+    group and per ensemble."""
+    groups = small_groups() + W.c3_batched_uneven(n_samples=3).groups
+    with qsg.Ensemble(groups, pt_every=5, swaplog_cap=8) as ref:
+        ref.init_spins()
+        ref.sweep(20, qsg.QSG_BATCHED)
+        want = ref.get_state()
+    with qsg.Ensemble(groups, pt_every=5, swaplog_cap=8, sweep_split=split) as ens:
+        ens.set_schedule(0, 16)
+        ens.init_spins()
+        ens.sweep(20, qsg.QSG_BATCHED | qsg.QSG_FUSED)
+        assert np.array_equal(ens.get_state(), want)
 
 
 def test_checkpoint_resume_is_bit_identical():

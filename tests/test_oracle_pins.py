@@ -292,6 +292,10 @@ def test_invariants_under_pt():
         Bsp, Bt, _ = og.recompute()
         assert np.array_equal(Bsp.reshape(-1), og.Bsp)
         assert np.array_equal(Bt.reshape(-1), og.Bt)
+        # one histogram entry per slot, lane and PT step; with L_tau slices
+        # the unsatisfied time bonds of a lane are even, so only even u occur
+        h = og.hist.reshape(ng, 1024)
+        assert np.all(h.sum(axis=1) == og.p * 64)
         # walker labels stay a permutation of the slots in every lane
         wk = og.walker.reshape(ng, 64)
         assert np.all(np.sort(wk, axis=0) == np.arange(ng)[:, None])
