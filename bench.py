@@ -51,6 +51,8 @@ def parse():
                     help="c2 (default): 64 samples, L=16, L_tau=128; c1: one sample, L=8, "
                          "L_tau=32; c3: 256 uneven samples; c4: L=24, L_tau=2048, 128 samples")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default colour-pass schedule instead of tuning it per shape")
     ap.add_argument("--cpu-sweeps", type=int, default=0,
                     help="oracle sweeps for the CPU baseline (0: about 15 s of work)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -96,10 +98,16 @@ def main():
     upd_per_sweep = wl.spin_updates_per_sweep()
     words_per_sweep = sum(g.words for g in wl.groups)
 
+    schedules = {}
+    if not args.no_autotune:
+        from paper_2402_03920_amd import autotune
+        print("[bench] tuning the colour-pass schedule per shape", file=sys.stderr, flush=True)
+        schedules = autotune.tune(wl.groups, log=lambda m: print(m, file=sys.stderr, flush=True))
     ens = qsg.Ensemble(wl.groups, pt_every=pe, swaplog_cap=64)
+    if schedules:
+        autotune.apply(ens, schedules)
     ens.init_spins()
     stream = ens.stream
-    flags = qsg.QSG_BATCHED | qsg.QSG_GRAPH
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -111,14 +119,28 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / 1e3
 
+    # the two batched forms of a PT chunk, both replayed as a HIP graph: one
+    # launch per colour pass over every group, or one fused launch for all the
+    # sweeps of the chunk (a block per slot); the faster one is the value
+    forms = {"per-pass": qsg.QSG_BATCHED | qsg.QSG_GRAPH,
+             "fused": qsg.QSG_BATCHED | qsg.QSG_GRAPH | qsg.QSG_FUSED}
+    probe = {}
+    for name, fl in forms.items():
+        ens.sweep(pe, fl)  # capture + warm
+        probe[name] = timed(lambda: ens.sweep(pe * 2, fl))
+    form = min(probe, key=probe.get)
+    flags = forms[form]
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     ens.sweep(pe * args.warmup, flags)
     torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} batched steps", file=sys.stderr, flush=True)
+    print(f"[bench] timing {args.steps} batched steps ({form})", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     sec = timed(lambda: ens.sweep(pe * args.steps, flags))
     wall = time.perf_counter() - t0
     ps_batched = sec / (pe * args.steps * upd_per_sweep) * 1e12
+    other = [n for n in forms if n != form][0]
+    sec_other = timed(lambda: ens.sweep(pe * args.plain_steps, forms[other]))
+    ps_other = sec_other / (pe * args.plain_steps * upd_per_sweep) * 1e12
 
     print(f"[bench] timing {args.plain_steps} plain steps", file=sys.stderr, flush=True)
     sec_plain = timed(lambda: ens.sweep(pe * args.plain_steps, qsg.QSG_PLAIN))
@@ -135,7 +157,7 @@ def main():
     ops_per_pass = words_per_pass * blocks * INSTR_PER_PHILOX_BLOCK
     achieved = ops_per_pass / pass_s / 1e12
     t, p = ens.counters()
-    energies = ens.energies()
+    physics = summarize(wl, ens)
     ens.close()
 
     result = {
@@ -155,7 +177,10 @@ def main():
             "workload": describe(wl, args.workload),
             "step": f"{pe} sweeps + energy pass + PT step + exchange pass, all samples",
             "spin_updates_per_step": upd_per_sweep * pe,
+            "batched_form": form,
+            "schedules": schedules,
         },
+        f"{other}_ps_per_spin_update": round(ps_other, 5),
         "plain_ps_per_spin_update": round(ps_plain, 5),
         "batched_speedup_vs_plain": round(ps_plain / ps_batched, 4),
         "spin_updates_per_s": upd_per_sweep * pe * args.steps / sec,
@@ -175,10 +200,39 @@ def main():
             "hbm_GBps_algorithmic": round(words_per_pass * 12 / pass_s / 1e9, 2),
         },
     }
+    result["physics"] = physics
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps)
     print(json.dumps(result), flush=True)
-    del energies
+
+
+def summarize(wl, ens):
+    """Per slot of the first group shape: mean space and time bond energy per
+    site (-Bsp/V, -Bt/V) and <q^2> of the replica-pair overlap, averaged over
+    the PT steps of the run and over samples of that shape (from the
+    library's integer sums)."""
+    import numpy as np
+    sums = ens.sums()
+    _, p = ens.counters()
+    g0 = wl.groups[0]
+    same = [i for i, g in enumerate(wl.groups)
+            if (g.L, g.L_tau, len(g.gammas)) == (g0.L, g0.L_tau, len(g0.gammas))]
+    if p == 0 or not same:
+        return {}
+    V = g0.L * g0.L * g0.L_tau
+    acc = np.zeros((len(g0.gammas), 192))
+    for i in same:
+        acc += sums[i]
+    acc /= len(same) * p
+    e_sp = -acc[:, 0:64].mean(axis=1) / V
+    e_t = -acc[:, 64:128].mean(axis=1) / V
+    q2 = acc[:, 160:192].mean(axis=1) / (V * V)
+    return {"shape": f"L={g0.L} L_tau={g0.L_tau} N_Gamma={len(g0.gammas)}",
+            "samples": len(same), "pt_steps": p,
+            "gamma": [round(float(x), 6) for x in g0.gammas],
+            "space_energy_per_site": [round(float(x), 6) for x in e_sp],
+            "time_energy_per_site": [round(float(x), 6) for x in e_t],
+            "q2": [round(float(x), 6) for x in q2]}
 
 
 def describe(wl, name):

@@ -113,8 +113,11 @@ struct WordState {
 
 // Words of one block still undecided after the first levels wait in LDS
 // (structure of arrays) and are finished by as few waves as possible.
+// Two counters alternate between consecutive calls of a block: a slow
+// thread may still be reading the previous call's count after a fast one has
+// cleared the counter for the next call.
 struct SweepQueue {
-    uint32_t count;
+    uint32_t count[2];
     uint32_t s[kSweepBlock];
     uint64_t w[kSweepBlock], s0[kSweepBlock], s1[kSweepBlock], s2[kSweepBlock];
     uint64_t t1[kSweepBlock], t2[kSweepBlock], acc[kSweepBlock], und[kSweepBlock];
@@ -253,10 +256,11 @@ __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, ui
 template <int R>
 __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
                                             uint32_t colour, uint32_t t, uint32_t idx, bool valid,
-                                            uint32_t q_split, SweepQueue& Q) {
+                                            uint32_t q_split, SweepQueue& Q, uint32_t parity) {
     using C = Classes<R>;
     const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
-    if (threadIdx.x == 0) Q.count = 0;
+    uint32_t& count = Q.count[parity & 1u];
+    if (threadIdx.x == 0) count = 0;
     __syncthreads();
     WordState st;
     st.acc = 0;
@@ -274,7 +278,7 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
         compare_levels<R>(G, g, t, st.s, M, th, 0, q_split, st.acc, st.und);
     }
     if (valid && st.und != 0) {
-        const uint32_t k = atomicAdd(&Q.count, 1u);
+        const uint32_t k = atomicAdd(&count, 1u);
         Q.s[k] = st.s;
         Q.w[k] = st.w;
         Q.s0[k] = st.s0;
@@ -288,7 +292,7 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
         S[st.s] = st.w ^ st.acc;
     }
     __syncthreads();
-    const uint32_t n = Q.count;
+    const uint32_t n = count;
     if (threadIdx.x < n) {
         const uint32_t k = threadIdx.x;
         WordState r;
@@ -310,14 +314,16 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
 }
 
 // S: the slot's spins (global memory, or a copy in LDS).
+// parity: alternate 0/1 between consecutive calls in one block.
 __device__ __forceinline__ void sweep_block_any(const GroupDev& G, uint64_t* S, uint32_t g,
                                                 uint32_t colour, uint32_t t, uint32_t idx,
-                                                bool valid, uint32_t q_split, SweepQueue& Q) {
+                                                bool valid, uint32_t q_split, SweepQueue& Q,
+                                                uint32_t parity) {
     switch (__builtin_amdgcn_readfirstlane(G.thr[g * kThrStride + 15])) {  // slot g's regime
-        case 0: sweep_block<0>(G, S, g, colour, t, idx, valid, q_split, Q); break;
-        case 1: sweep_block<1>(G, S, g, colour, t, idx, valid, q_split, Q); break;
-        case 2: sweep_block<2>(G, S, g, colour, t, idx, valid, q_split, Q); break;
-        default: sweep_block<3>(G, S, g, colour, t, idx, valid, q_split, Q); break;
+        case 0: sweep_block<0>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
+        case 1: sweep_block<1>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
+        case 2: sweep_block<2>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
+        default: sweep_block<3>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
     }
 }
 
@@ -339,7 +345,8 @@ k_half_sweep(const GroupDev G, uint32_t colour, const uint32_t* __restrict__ ctr
     const uint32_t b = xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const uint32_t g = b / gridDim.x;
     const uint32_t idx = (b - g * gridDim.x) * kSweepBlock + threadIdx.x;
-    sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q);
+    sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
+                    0);
 }
 
 __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ prefix,
@@ -365,7 +372,8 @@ k_half_sweep_batched(const GroupDev* __restrict__ groups, const uint32_t* __rest
     const uint32_t nb = sweep_blocks_per_slot(G.V);
     const uint32_t g = local / nb;
     const uint32_t idx = (local - g * nb) * kSweepBlock + threadIdx.x;
-    sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q);
+    sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
+                    0);
 }
 
 // ---------------------------------------------------------------------------
@@ -392,11 +400,12 @@ k_chunk_fused(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ 
         __syncthreads();
     }
     const uint32_t t0 = ctr[0];
+    uint32_t call = 0;
     for (uint32_t it = 0; it < n_sweeps; ++it) {
         for (uint32_t colour = 0; colour < 2; ++colour) {
             for (uint32_t base = 0; base < half; base += kSweepBlock) {
                 const uint32_t idx = base + threadIdx.x;
-                sweep_block_any(G, S, g, colour, t0 + it, idx, idx < half, G.q_split, Q);
+                sweep_block_any(G, S, g, colour, t0 + it, idx, idx < half, G.q_split, Q, call++);
             }
             __syncthreads();  // the next colour reads what this one wrote
         }
@@ -731,10 +740,9 @@ __global__ void k_init_state(const GroupDev G) {
         G.E[(g * 64 + j) * 2 + 0] = 0;
         G.E[(g * 64 + j) * 2 + 1] = 0;
     }
-    for (uint32_t g = j; g < N; g += 64) {
-        G.lastmask[g] = 0;
-        if (g + 1 < N) G.acc[g] = 0;
-    }
+    const uint32_t pairs = N > 1 ? N - 1 : 1;  // the acc region has max(N-1, 1) entries
+    for (uint32_t g = j; g < N; g += 64) G.lastmask[g] = 0;
+    for (uint32_t g = j; g < pairs; g += 64) G.acc[g] = 0;
     const size_t nlog = (size_t)G.log_cap * (N > 1 ? N - 1 : 1);
     for (size_t i = j; i < nlog; i += 64) G.swaplog[i] = 0;
 }

@@ -117,6 +117,9 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--c3-samples", type=int, default=256)
+    ap.add_argument("--focus-sweeps", type=int, default=50000,
+                    help="second, longer comparison on the samples whose learned ladder "
+                         "passed the floor (0: skip)")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
@@ -136,6 +139,11 @@ def main(argv=None):
     log(f"[ladder] trained on {len(X)} runs: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
     ev = W.c5_eval(n_samples=args.eval_samples).groups
     res = compare(model, ev, args.eval_sweeps, log=log)
+    if args.focus_sweeps:
+        keep = [g for g, a in zip(ev, res["predicted_acceptance"]) if a >= 0.2]
+        if keep:
+            log(f"[ladder] focused comparison: {len(keep)} samples, {args.focus_sweeps} sweeps")
+            res["focused"] = compare(model, keep, args.focus_sweeps, log=log)
     res["train"] = {"runs": int(len(X)), "loss_history": hist, "steps": args.steps,
                     "train_sweeps": args.train_sweeps}
     res["elapsed_s"] = time.time() - t0
@@ -144,8 +152,17 @@ def main(argv=None):
         with open(args.out, "w") as f:
             f.write(js)
     print(json.dumps({k: v for k, v in res.items()
-                      if k in ("geometric", "learned", "paired_round_trip_gain",
-                               "fallback_fraction")}, default=lambda o: None)[:4000])
+                      if k in ("paired_round_trip_gain", "fallback_fraction")}))
+    for key in ("geometric", "learned"):
+        print(key, {k: res[key][k] for k in ("round_trips", "round_trips_per_hour",
+                                              "mean_round_trip_pt_steps", "acceptance_min",
+                                              "acceptance_mean")})
+    if "focused" in res:
+        f = res["focused"]
+        print("focused", f["paired_round_trip_gain"],
+              {k: (f["geometric"][k], f["learned"][k]) for k in
+               ("round_trips", "round_trips_per_hour", "mean_round_trip_pt_steps",
+                "acceptance_min", "acceptance_std_within_sample_mean")})
 
 
 if __name__ == "__main__":
