@@ -40,6 +40,41 @@ def required_blocks_per_word(lanes: int = 64) -> float:
     return sum(1.0 - (1.0 - 4.0 ** (-(k - 1))) ** lanes for k in range(1, 17))
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c2_traffic.txt")
+KERNEL_SOURCES = ("paper_2402_03920_amd/csrc/qsg_kernels.hip",
+                  "paper_2402_03920_amd/csrc/qsg_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the colour pass on the bench workload, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a plain
+    copy's counters), or None when that summary was taken on other kernel
+    sources or another workload."""
+    if workload != "c2" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(vals["fetch_bytes_per_launch"]) + int(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,7 +227,9 @@ def main():
             "peak": round(PEAK_VALU_TOPS, 4),
             "unit": "T VALU lane-instructions/s",
             "frac": round(achieved / PEAK_VALU_TOPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": int(words_per_pass * 12),
             "avg_launch_us": round(pass_s * 1e6, 3),
             "algorithmic_ops_per_launch": ops_per_pass,
             "model": f"required Philox work only: {blocks:.4f} blocks/word x "

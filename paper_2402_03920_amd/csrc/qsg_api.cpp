@@ -133,23 +133,43 @@ bool make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config& cfg,
 // Which specialised class list covers every class of this slot that is not
 // accepted outright (threshold below 2^32-1): 0, 1, 2, or 3 for the generic
 // fifteen-class update.  The lists match the kernels' Classes<R>.
+const int kRegimeLists[3][7][2] = {
+    {{0, 0}, {1, 0}, {2, 0}, {3, 0}, {4, 0}, {0, 1}, {1, 1}},
+    {{0, 0}, {1, 0}, {2, 0}, {3, 0}, {0, 1}, {1, 1}, {0, 2}},
+    {{0, 0}, {1, 0}, {2, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}},
+};
+
 uint32_t class_regime(const uint32_t* thr15) {
-    static const int lists[3][7][2] = {
-        {{0, 0}, {1, 0}, {2, 0}, {3, 0}, {4, 0}, {0, 1}, {1, 1}},
-        {{0, 0}, {1, 0}, {2, 0}, {3, 0}, {0, 1}, {1, 1}, {0, 2}},
-        {{0, 0}, {1, 0}, {2, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}},
-    };
     for (uint32_t r = 0; r < 3; ++r) {
         bool covered = true;
         for (int c = 0; c < 15 && covered; ++c) {
             if (thr15[c] == 0xFFFFFFFFu) continue;
             bool in = false;
-            for (int i = 0; i < 7; ++i) in |= (lists[r][i][0] * 3 + lists[r][i][1] == c);
+            for (int i = 0; i < 7; ++i)
+                in |= (kRegimeLists[r][i][0] * 3 + kRegimeLists[r][i][1] == c);
             covered = in;
         }
         if (covered) return r;
     }
     return 3;
+}
+
+// Level picks of a slot in regime r < 3: per comparison level (bit 31 - b of
+// the thresholds, b = 0..31) the set of the regime's seven classes whose
+// threshold bit is 1, or its complement with bit 7 set when that is smaller,
+// so the colour pass ORs at most three class masks per level.
+void level_picks(const uint32_t* thr15, uint32_t r, uint32_t* out8) {
+    for (int w = 0; w < 8; ++w) out8[w] = 0;
+    if (r > 2) return;
+    for (int b = 0; b < 32; ++b) {
+        uint32_t set = 0;
+        for (int i = 0; i < 7; ++i) {
+            const int c = kRegimeLists[r][i][0] * 3 + kRegimeLists[r][i][1];
+            set |= ((thr15[c] >> (31 - b)) & 1u) << i;
+        }
+        const uint32_t pick = __builtin_popcount(set) > 3 ? ((~set & 0x7Fu) | 0x80u) : set;
+        out8[b >> 2] |= pick << (8 * (b & 3));
+    }
 }
 
 }  // namespace
@@ -386,6 +406,7 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         g.div_half_row = qsg::make_divisor(d.L / 2);
         g.div_plane = qsg::make_divisor(d.L * d.L);
         g.div_row = qsg::make_divisor(d.L);
+        g.div_blocks = qsg::make_divisor(qsg::sweep_blocks_per_slot(g.V));
         g.sw_cap = swap_cap_of(d);
         g.log_cap = cfg->swaplog_cap;
         g.q_split = cfg->sweep_split ? (cfg->sweep_split > 16 ? 16 : cfg->sweep_split) : 4;
@@ -477,7 +498,9 @@ qsg_status qsg_set_gamma_ladder(qsg_ctx* c, uint32_t group, const double* gamma)
     if (rc != 0) return fail(c, QSG_E_UNSUPPORTED, "%s", err);
     for (uint32_t i = 0; i < N; ++i) {
         for (int k = 0; k < 15; ++k) thr[i * qsg::kThrStride + k] = thr15[i * 15 + k];
-        thr[i * qsg::kThrStride + 15] = class_regime(&thr15[i * 15]);
+        const uint32_t r = class_regime(&thr15[i * 15]);
+        thr[i * qsg::kThrStride + 15] = r;
+        level_picks(&thr15[i * 15], r, &thr[i * qsg::kThrStride + qsg::kLevelPicks]);
     }
     for (uint32_t i = 0; i < pairs; ++i) eq32[i] = eq[i];
     hipStream_t s = c->stream;

@@ -22,8 +22,13 @@ struct RoundTrip {
 constexpr int kCntStride = 64 + 64 + 32;  // int32 per slot
 // Per-slot measurement sums: Bsp[64], Bt[64], q[32], q^2[32] as int64.
 constexpr int kSumStride = 192;
-// Thresholds per slot, padded.
-constexpr int kThrStride = 16;
+// Per-slot table: [0, 15) thresholds of the fifteen classes, [15] the class
+// regime, [16, 24) the level picks (one byte per comparison level, most
+// significant first, four to a word): for the seven classes of regimes 0-2,
+// bits 0-6 mark the classes whose threshold has a 1 at that level, or, when
+// more than three do, bits 0-6 mark those with a 0 and bit 7 is set.
+constexpr int kThrStride = 32;
+constexpr int kLevelPicks = 16;
 // Histogram of the unsatisfied time bonds u = (V - Bt)/2 per slot, taken at
 // every PT step before the exchanges: bin = u * kHistBins / (V + 1).
 constexpr int kHistBins = 1024;
@@ -59,11 +64,12 @@ struct GroupDev {
     uint32_t log_cap;     // rows of the swap log
     uint32_t q_split;     // colour-pass schedule: Philox blocks before packing
     Divisor div_half_plane, div_half_row, div_plane, div_row;
+    Divisor div_blocks;   // colour-pass blocks per slot
     uint64_t* spins;          // [N][Ltau][L][L]
     uint64_t* Jx;             // [L*L]
     uint64_t* Jy;             // [L*L]
     const uint64_t* jseed;    // [64] coupling keys
-    uint32_t* thr;            // [N][16]; [15] = class regime of the slot
+    uint32_t* thr;            // [N][kThrStride] thresholds, regime, level picks
     uint32_t* sw_thr;         // [N-1][sw_cap]
     uint32_t* sw_len;         // [N-1]
     uint32_t* sw_eq;          // [N-1]

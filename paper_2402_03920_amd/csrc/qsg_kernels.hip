@@ -34,13 +34,21 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
+// In the colour pass only counter word 0 (the site) differs between lanes,
+// so the first two rounds group their xors to keep the block-uniform parts
+// on the scalar unit: round 0 has c.y, c.z, c.w uniform, round 1 c.x, c.y.
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)c.x * kM0;
         const uint64_t p1 = (uint64_t)c.z * kM1;
-        c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
-                       xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
+        const uint32_t h0 = (uint32_t)(p0 >> 32), h1 = (uint32_t)(p1 >> 32);
+        if (r == 0)
+            c = make_uint4(h1 ^ (c.y ^ k0), (uint32_t)p1, h0 ^ (c.w ^ k1), (uint32_t)p0);
+        else if (r == 1)
+            c = make_uint4(h1 ^ (c.y ^ k0), (uint32_t)p1, (h0 ^ k1) ^ c.w, (uint32_t)p0);
+        else
+            c = make_uint4(xor3(h1, c.y, k0), (uint32_t)p1, xor3(h0, c.w, k1), (uint32_t)p0);
         k0 += kW0;
         k1 += kW1;
     }
@@ -207,21 +215,50 @@ constexpr int kAndOr = 0xEA;      // (a & b) | c
 constexpr int kAndAndNot = 0x40;  // a & b & ~c
 constexpr int kAndXnor = 0x90;    // a & ~(b ^ c)
 
+// Level picks of the blocks q >= q0, two bytes per block, as a 256-bit
+// block-uniform shift register (see kLevelPicks).
+struct Picks {
+    uint64_t w[4];
+    __device__ __forceinline__ void load(const uint32_t* __restrict__ thr, uint32_t q0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            w[i] = lo_hi(__builtin_amdgcn_readfirstlane(thr[kLevelPicks + 2 * i]),
+                         __builtin_amdgcn_readfirstlane(thr[kLevelPicks + 2 * i + 1]));
+#pragma unroll 1
+        for (uint32_t q = 0; q < q0; ++q) next();
+    }
+    __device__ __forceinline__ uint32_t current() const { return (uint32_t)w[0] & 0xFFFFu; }
+    __device__ __forceinline__ void next() {
+        w[0] = (w[0] >> 16) | (w[1] << 48);
+        w[1] = (w[1] >> 16) | (w[2] << 48);
+        w[2] = (w[2] >> 16) | (w[3] << 48);
+        w[3] >>= 16;
+    }
+};
+
 // Compare the lanes' bit-sliced Philox numbers with their class thresholds,
 // most significant level first, for blocks q0 <= q < q1 while any lane of
 // the wave is undecided.  Block q (counter (s, t, g<<4 | q, gid)) carries
-// levels 2q and 2q+1.  Per level, on each 32-bit half: the threshold bit
-// plane T (one bitop3 per class), then
+// levels 2q and 2q+1.  Per level, on each 32-bit half, with T the plane of
+// the lanes' threshold bits and W the level of the random numbers:
 //   acc |= und & T & ~W   (r has 0 where thr has 1: r < thr, accepted)
 //   und &= ~(T ^ W)       (still equal so far).
+// Regimes 0-2 build T from the slot's level pick: a block-uniform branch per
+// class skips the classes outside it, so at most three masks are combined;
+// the class masks are disjoint, so T = inv ^ (xor of the picked masks), with
+// inv = ~0 for a complemented pick, is exact on every lane still undecided.
+// Regime 3 (any table) ORs all fifteen masks, each ANDed with its bit.
 template <int R>
 __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, uint32_t t,
                                                uint32_t s, const uint64_t (&M)[Classes<R>::n],
-                                               const uint32_t (&th)[Classes<R>::n], uint32_t q0,
+                                               const uint32_t (&th)[Classes<R>::n],
+                                               const uint32_t* __restrict__ thr, uint32_t q0,
                                                uint32_t q1, uint64_t& acc, uint64_t& und) {
     using C = Classes<R>;
     uint32_t acc_lo = (uint32_t)acc, acc_hi = (uint32_t)(acc >> 32);
     uint32_t und_lo = (uint32_t)und, und_hi = (uint32_t)(und >> 32);
+    Picks P;
+    if (R < 3) P.load(thr, q0);
 #pragma unroll 1
     for (uint32_t q = q0; q < q1; ++q) {
         if (!__any((und_lo | und_hi) != 0)) break;  // every lane of the wave is decided
@@ -230,19 +267,33 @@ __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, ui
         const uint32_t lev_hi[2] = {o.y, o.w};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const uint32_t bit = 31u - (2u * q + (uint32_t)h);
             uint32_t T_lo = 0, T_hi = 0;
+            if (R < 3) {
+                const uint32_t pick = (P.current() >> (8 * h)) & 0xFFu;
+                T_lo = T_hi = 0u - (pick >> 7);
 #pragma unroll
-            for (int i = 0; i < C::n; ++i) {
-                const uint32_t B = 0u - ((th[i] >> bit) & 1u);  // block-uniform 0 or ~0
-                T_lo = BITOP3((uint32_t)M[i], B, T_lo, kAndOr);
-                T_hi = BITOP3((uint32_t)(M[i] >> 32), B, T_hi, kAndOr);
+                for (int i = 0; i < C::n; ++i) {
+                    if (pick & (1u << i)) {
+                        asm volatile("");  // keep the uniform branch: no select of both sides
+                        T_lo ^= (uint32_t)M[i];
+                        T_hi ^= (uint32_t)(M[i] >> 32);
+                    }
+                }
+            } else {
+                const uint32_t bit = 31u - (2u * q + (uint32_t)h);
+#pragma unroll
+                for (int i = 0; i < C::n; ++i) {
+                    const uint32_t B = 0u - ((th[i] >> bit) & 1u);  // block-uniform 0 or ~0
+                    T_lo = BITOP3((uint32_t)M[i], B, T_lo, kAndOr);
+                    T_hi = BITOP3((uint32_t)(M[i] >> 32), B, T_hi, kAndOr);
+                }
             }
             acc_lo |= BITOP3(und_lo, T_lo, lev_lo[h], kAndAndNot);
             acc_hi |= BITOP3(und_hi, T_hi, lev_hi[h], kAndAndNot);
             und_lo = BITOP3(und_lo, T_lo, lev_lo[h], kAndXnor);
             und_hi = BITOP3(und_hi, T_hi, lev_hi[h], kAndXnor);
         }
+        if (R < 3) P.next();
     }
     acc = lo_hi(acc_lo, acc_hi);
     und = lo_hi(und_lo, und_hi);
@@ -275,7 +326,7 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
         for (int i = 0; i < C::n; ++i) live |= M[i];
         st.acc = ~live;  // lanes outside the listed classes: dE <= 0, accepted
         st.und = live;
-        compare_levels<R>(G, g, t, st.s, M, th, 0, q_split, st.acc, st.und);
+        compare_levels<R>(G, g, t, st.s, M, th, thr, 0, q_split, st.acc, st.und);
     }
     if (valid && st.und != 0) {
         const uint32_t k = atomicAdd(&count, 1u);
@@ -307,7 +358,7 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
         uint64_t M[C::n];
         uint32_t th[C::n];
         class_masks<R>(r, thr, M, th);
-        compare_levels<R>(G, g, t, r.s, M, th, q_split, 16, acc, und);
+        compare_levels<R>(G, g, t, r.s, M, th, thr, q_split, 16, acc, und);
         acc |= und;  // equal on all 32 bits: r == thr, accepted
         if (acc) S[r.s] = r.w ^ acc;
     }
@@ -341,9 +392,9 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
 __global__ void __launch_bounds__(kSweepBlock)
 k_half_sweep(const GroupDev G, uint32_t colour, const uint32_t* __restrict__ ctr, uint32_t t_add) {
     __shared__ SweepQueue Q;
-    const uint32_t t = ctr[0] + t_add;
+    const uint32_t t = __builtin_amdgcn_readfirstlane(ctr[0] + t_add);
     const uint32_t b = xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const uint32_t g = b / gridDim.x;
+    const uint32_t g = fast_div(b, G.div_blocks);  // b / gridDim.x on the scalar unit
     const uint32_t idx = (b - g * gridDim.x) * kSweepBlock + threadIdx.x;
     sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
                     0);
@@ -364,13 +415,13 @@ k_half_sweep_batched(const GroupDev* __restrict__ groups, const uint32_t* __rest
                      uint32_t n_groups, uint32_t colour, const uint32_t* __restrict__ ctr,
                      uint32_t t_add) {
     __shared__ SweepQueue Q;
-    const uint32_t t = ctr[0] + t_add;
+    const uint32_t t = __builtin_amdgcn_readfirstlane(ctr[0] + t_add);
     const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
     const uint32_t gi = find_group(prefix, n_groups, b);
     const GroupDev G = uniform_record(groups + gi);
-    const uint32_t local = b - prefix[gi];
+    const uint32_t local = __builtin_amdgcn_readfirstlane(b - prefix[gi]);
     const uint32_t nb = sweep_blocks_per_slot(G.V);
-    const uint32_t g = local / nb;
+    const uint32_t g = fast_div(local, G.div_blocks);  // local / nb on the scalar unit
     const uint32_t idx = (local - g * nb) * kSweepBlock + threadIdx.x;
     sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
                     0);
@@ -390,7 +441,7 @@ k_chunk_fused(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ 
     __shared__ SweepQueue Q;
     const uint32_t gi = find_group(slot_prefix, n_groups, blockIdx.x);
     const GroupDev G = uniform_record(groups + gi);
-    const uint32_t g = blockIdx.x - slot_prefix[gi];
+    const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x - slot_prefix[gi]);
     const uint32_t V = G.V, half = V >> 1;
     uint64_t* Sg = G.spins + (size_t)g * V;
     const bool in_lds = V <= lds_words;
@@ -399,7 +450,7 @@ k_chunk_fused(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ 
         for (uint32_t i = threadIdx.x; i < V; i += kSweepBlock) lds_spins[i] = Sg[i];
         __syncthreads();
     }
-    const uint32_t t0 = ctr[0];
+    const uint32_t t0 = __builtin_amdgcn_readfirstlane(ctr[0]);
     uint32_t call = 0;
     for (uint32_t it = 0; it < n_sweeps; ++it) {
         for (uint32_t colour = 0; colour < 2; ++colour) {
