@@ -194,6 +194,7 @@ def main():
     t, p = ens.counters()
     physics = summarize(wl, ens)
     ens.close()
+    ceiling = philox_ceiling()
 
     result = {
         "metric": "ps/spin-update (1 GPU) batched vs plain",
@@ -237,10 +238,36 @@ def main():
             "hbm_GBps_algorithmic": round(words_per_pass * 12 / pass_s / 1e9, 2),
         },
     }
+    required_rate = words_per_pass * blocks / pass_s
+    result["philox_ceiling"] = dict(ceiling, sweep_required_blocks_per_s=required_rate,
+                                    sweep_frac_of_ceiling=round(required_rate / ceiling["blocks_per_s"], 4))
     result["physics"] = physics
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps)
     print(json.dumps(result), flush=True)
+
+
+def philox_ceiling(threads: int = 1 << 20, blocks: int = 2048, reps: int = 3):
+    """Philox4x32-10 blocks per second of the whole GPU with nothing else in
+    the way (the library's probe kernel: the colour pass's counter shape, one
+    per-thread word), best of `reps` launches timed with events on their
+    stream."""
+    import torch
+    from paper_2402_03920_amd import qsg
+    out = torch.empty(threads, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    qsg.philox_probe(out, threads, 64, 1, s)  # warm-up
+    best = float("inf")
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        qsg.philox_probe(out, threads, blocks, 1, s)
+        b.record(s)
+        s.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    return {"blocks_per_s": threads * blocks / best,
+            "probe": f"{threads} threads x {blocks} blocks, best of {reps}"}
 
 
 def summarize(wl, ens):

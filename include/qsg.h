@@ -203,6 +203,16 @@ void qsg_destroy(qsg_ctx* ctx);
  * = Philox(ctr = in[6i..6i+3], key = in[6i+4..6i+5]).  Device pointers. */
 qsg_status qsg_philox(const uint32_t* d_in, uint32_t* d_out, uint32_t n, void* hip_stream);
 
+/* Random-number ceiling of the device (measurement only; the generator of
+ * Sec. 2.1.1): thread i < n_threads generates `blocks` Philox4x32-10 blocks
+ * with counters (i, 0, b, 0), b < blocks, under key (key lo, key hi) -- the
+ * counter shape of the colour pass, one per-thread word -- and writes the xor
+ * of all 4*blocks output words to d_out[i] (device, n_threads words, caller
+ * owned).  Asynchronous on hip_stream.  Timing it gives Philox blocks per
+ * second with nothing else in the way. */
+qsg_status qsg_philox_probe(uint32_t n_threads, uint32_t blocks, uint64_t key, uint32_t* d_out,
+                            void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Learned Gamma ladder: a 6 -> 128 -> 128 -> 128 -> 32 MLP (exact-erf GELU on
  * the hidden layers) mapping (L, L_tau, beta, frustrated-plaquette fraction,

@@ -880,6 +880,15 @@ qsg_status qsg_philox(const uint32_t* d_in, uint32_t* d_out, uint32_t n, void* h
     return QSG_OK;
 }
 
+qsg_status qsg_philox_probe(uint32_t n_threads, uint32_t blocks, uint64_t key, uint32_t* d_out,
+                            void* hip_stream) {
+    if (!d_out && n_threads) return fail(nullptr, QSG_E_INVALID, "null buffer");
+    hipError_t e = qsg::launch_philox_probe(d_out, n_threads, blocks, key,
+                                            static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(nullptr, QSG_E_DEVICE, "philox probe launch: %s", hipGetErrorString(e));
+    return QSG_OK;
+}
+
 uint32_t qsg_mlp_param_count(void) { return (uint32_t)qsg::kMlpParams; }
 
 size_t qsg_mlp_workspace_floats(uint32_t B) { return qsg::mlp_ws_floats((int)B); }

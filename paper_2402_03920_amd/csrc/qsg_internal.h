@@ -103,6 +103,8 @@ hipError_t launch_swap_apply(const GroupDev& g, hipStream_t s);
 hipError_t launch_zero32(void* p, size_t n_words32, hipStream_t s);
 
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, uint32_t n, hipStream_t s);
+hipError_t launch_philox_probe(uint32_t* out, uint32_t n, uint32_t blocks, uint64_t key,
+                              hipStream_t s);
 
 // Batched: one launch per pass over all groups.  `prefix[i]` is the first
 // block of group i (prefix[n_groups] = total blocks); a block finds its
@@ -132,6 +134,7 @@ __host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V);
 __host__ __device__ inline uint32_t swap_blocks(uint32_t V);
 
 constexpr int kSweepBlock = 256;   // threads per block of a colour pass
+constexpr uint32_t kWaveSize = 64;
 constexpr int kEnergyWords = 32;   // words per thread in the energy pass
 constexpr int kEnergyBlock = 256;
 constexpr int kSwapBlock = 256;

@@ -109,42 +109,76 @@ __device__ __forceinline__ uint64_t all_if(uint32_t v, uint32_t bit) {
     return 0ull - (uint64_t)((v >> bit) & 1u);  // block-uniform 0 or ~0
 }
 
+// Three-input bitwise operation of gfx950 (v_bitop3_b32); the immediate is
+// the truth table f(0xF0, 0xCC, 0xAA) of the operand order (a, b, c).
+#define BITOP3(a, b, c, table) __builtin_amdgcn_bitop3_b32((a), (b), (c), (table))
+constexpr int kAndOr = 0xEA;      // (a & b) | c
+constexpr int kAndAndNot = 0x40;  // a & b & ~c
+constexpr int kAndXnor = 0x90;    // a & ~(b ^ c)
+constexpr int kXor3 = 0x96;       // a ^ b ^ c
+constexpr int kMajority = 0xE8;   // at least two of a, b, c
+constexpr int kXorAnd = 0x78;     // a ^ (b & c)
+constexpr int kAnd3 = 0x80;       // a & b & c
+constexpr int kAndNotAnd = 0x20;  // a & ~b & c
+constexpr int kNor3 = 0x01;       // ~(a | b | c)
+constexpr int kEqEq = 0x81;       // a == b and a == c
+constexpr int kNeNe = 0x18;       // a != b and a != c
+
+template <int T>
+__device__ __forceinline__ uint64_t bop3(uint64_t a, uint64_t b, uint64_t c) {
+    return lo_hi(BITOP3((uint32_t)a, (uint32_t)b, (uint32_t)c, T),
+                 BITOP3((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), T));
+}
+
 // Per-word state of the comparison: the class planes it needs (bit-sliced
-// n_s = s2 s1 s0 and the two time-bond planes t1, t2), the lanes accepted so
+// n_s = s2 s1 s0 and one-hot planes of n_t = 0, 1, 2), the lanes accepted so
 // far and the lanes still undecided.
 struct WordState {
     uint32_t s;  // flat site index (RNG counter word 0)
     uint64_t w;  // centre word before the update
-    uint64_t s0, s1, s2, t1, t2;
+    uint64_t s0, s1, s2, nt0, nt1, nt2;
     uint64_t acc, und;
 };
 
 // Words of one block still undecided after the first levels wait in LDS
-// (structure of arrays) and are finished by as few waves as possible.
-// Two counters alternate between consecutive calls of a block: a slow
-// thread may still be reading the previous call's count after a fast one has
-// cleared the counter for the next call.
+// (structure of arrays) and are finished by as few waves as possible.  The
+// n_t = 1 plane is not stored: the three n_t planes are one-hot.
+// Two pairs of counters alternate between consecutive calls of a block: a
+// slow thread may still be reading the previous call's count after a fast
+// one has cleared the counters for the next call.
 struct SweepQueue {
-    uint32_t count[2];
+    uint32_t count[4];
     uint32_t s[kSweepBlock];
     uint64_t w[kSweepBlock], s0[kSweepBlock], s1[kSweepBlock], s2[kSweepBlock];
-    uint64_t t1[kSweepBlock], t2[kSweepBlock], acc[kSweepBlock], und[kSweepBlock];
+    uint64_t nt0[kSweepBlock], nt2[kSweepBlock], acc[kSweepBlock], und[kSweepBlock];
 };
 
-// Load the neighbourhood of colour-c word `idx` of a slot and count
-// unsatisfied bonds.  Colour-c words of a slot are numbered plane by plane,
-// row by row: idx = tau*(L*L/2) + y*(L/2) + xh, x = 2*xh + ((c + y + tau) & 1).
-__device__ __forceinline__ WordState load_word(const GroupDev& G, const uint64_t* __restrict__ S,
-                                               uint32_t colour, uint32_t idx) {
+// Spin and coupling words are addressed as base + 32-bit byte offset (a
+// slot and the coupling arrays are far below 4 GiB), so global accesses keep
+// the base in SGPRs and only the offset in a VGPR.  The fused kernel may hold
+// a slot in LDS and addresses it generically.
+typedef char __attribute__((address_space(1))) GlobalByte;
+template <bool kGlobal>
+__device__ __forceinline__ uint64_t load64(const uint64_t* base, uint32_t i) {
+    if (kGlobal)
+        return *(const uint64_t __attribute__((address_space(1)))*)((const GlobalByte*)base + i * 8u);
+    return base[i];
+}
+template <bool kGlobal>
+__device__ __forceinline__ void store64(uint64_t* base, uint32_t i, uint64_t v) {
+    if (kGlobal)
+        *(uint64_t __attribute__((address_space(1)))*)((GlobalByte*)base + i * 8u) = v;
+    else
+        base[i] = v;
+}
+
+// Site (x, y, tau): its six neighbours and four couplings, the unsatisfied
+// bonds and their bit-sliced counts.
+template <bool kGlobal>
+__device__ __forceinline__ WordState load_site(const GroupDev& G, const uint64_t* __restrict__ S,
+                                               uint32_t x, uint32_t y, uint32_t tau) {
     const uint32_t L = G.L;
     const uint32_t P = L * L;
-    const uint32_t half_plane = P >> 1;
-    const uint32_t half_row = L >> 1;
-    const uint32_t tau = fast_div(idx, G.div_half_plane);
-    const uint32_t rem = idx - tau * half_plane;
-    const uint32_t y = fast_div(rem, G.div_half_row);
-    const uint32_t x = 2 * (rem - y * half_row) + ((colour + y + tau) & 1u);
-
     const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
     const uint32_t xm = (x == 0) ? L - 1 : x - 1;
     const uint32_t yp = (y + 1 == L) ? 0 : y + 1;
@@ -156,33 +190,49 @@ __device__ __forceinline__ WordState load_word(const GroupDev& G, const uint64_t
 
     WordState st;
     st.s = plane + row + x;
-    const uint64_t w = S[st.s];
-    const uint64_t nxp = S[plane + row + xp];
-    const uint64_t nxm = S[plane + row + xm];
-    const uint64_t nyp = S[plane + yp * L + x];
-    const uint64_t nym = S[plane + ym * L + x];
-    const uint64_t ntp = S[tp * P + row + x];
-    const uint64_t ntm = S[tm * P + row + x];
-    const uint64_t jxp = G.Jx[row + x];
-    const uint64_t jxm = G.Jx[row + xm];  // the -x bond is the +x bond of x-1
-    const uint64_t jyp = G.Jy[row + x];
-    const uint64_t jym = G.Jy[ym * L + x];
+    const uint64_t w = load64<kGlobal>(S, st.s);
+    const uint64_t nxp = load64<kGlobal>(S, plane + row + xp);
+    const uint64_t nxm = load64<kGlobal>(S, plane + row + xm);
+    const uint64_t nyp = load64<kGlobal>(S, plane + yp * L + x);
+    const uint64_t nym = load64<kGlobal>(S, plane + ym * L + x);
+    const uint64_t ntp = load64<kGlobal>(S, tp * P + row + x);
+    const uint64_t ntm = load64<kGlobal>(S, tm * P + row + x);
+    const uint64_t jxp = load64<true>(G.Jx, row + x);
+    const uint64_t jxm = load64<true>(G.Jx, row + xm);  // the -x bond is the +x bond of x-1
+    const uint64_t jyp = load64<true>(G.Jy, row + x);
+    const uint64_t jym = load64<true>(G.Jy, ym * L + x);
 
-    // unsatisfied-bond planes and their bit-sliced counts
-    const uint64_t u1 = w ^ nxp ^ jxp, u2 = w ^ nxm ^ jxm;
-    const uint64_t u3 = w ^ nyp ^ jyp, u4 = w ^ nym ^ jym;
-    const uint64_t a0 = u1 ^ u2, a1 = u1 & u2;
-    const uint64_t b0 = u3 ^ u4, b1 = u3 & u4;
-    const uint64_t c0 = a0 & b0;
+    // unsatisfied space bonds u = w ^ neighbour ^ coupling and their count
+    // n_s = s2 s1 s0: a full adder over u1..u3, then u4 added to its sum
+    const uint64_t u1 = bop3<kXor3>(w, nxp, jxp), u2 = bop3<kXor3>(w, nxm, jxm);
+    const uint64_t u3 = bop3<kXor3>(w, nyp, jyp), u4 = bop3<kXor3>(w, nym, jym);
+    const uint64_t sum = bop3<kXor3>(u1, u2, u3), carry = bop3<kMajority>(u1, u2, u3);
     st.w = w;
-    st.s0 = a0 ^ b0;
-    st.s1 = a1 ^ b1 ^ c0;
-    st.s2 = (a1 & b1) | (c0 & (a1 ^ b1));
-    st.t1 = w ^ ntp;
-    st.t2 = w ^ ntm;
+    st.s0 = sum ^ u4;
+    st.s1 = bop3<kXorAnd>(carry, sum, u4);
+    st.s2 = bop3<kAnd3>(carry, sum, u4);
+    // unsatisfied time bonds n_t as one-hot planes
+    st.nt0 = bop3<kEqEq>(w, ntp, ntm);
+    st.nt1 = ntp ^ ntm;
+    st.nt2 = bop3<kNeNe>(w, ntp, ntm);
     st.acc = 0;
     st.und = 0;
     return st;
+}
+
+// Load the neighbourhood of colour-c word `idx` of a slot and count
+// unsatisfied bonds.  Colour-c words of a slot are numbered plane by plane,
+// row by row: idx = tau*(L*L/2) + y*(L/2) + xh, x = 2*xh + ((c + y + tau) & 1).
+template <bool kGlobal>
+__device__ __forceinline__ WordState load_word(const GroupDev& G, const uint64_t* __restrict__ S,
+                                               uint32_t colour, uint32_t idx) {
+    const uint32_t half_plane = (G.L * G.L) >> 1;
+    const uint32_t half_row = G.L >> 1;
+    const uint32_t tau = fast_div(idx, G.div_half_plane);
+    const uint32_t rem = idx - tau * half_plane;
+    const uint32_t y = fast_div(rem, G.div_half_row);
+    const uint32_t x = 2 * (rem - y * half_row) + ((colour + y + tau) & 1u);
+    return load_site<kGlobal>(G, S, x, y, tau);
 }
 
 // One-hot masks of the listed classes and the slot's thresholds for them.
@@ -191,29 +241,24 @@ __device__ __forceinline__ void class_masks(const WordState& st, const uint32_t*
                                             uint64_t (&M)[Classes<R>::n],
                                             uint32_t (&th)[Classes<R>::n]) {
     using C = Classes<R>;
-    uint64_t NS[5], NT[3];
-    NS[0] = ~(st.s2 | st.s1 | st.s0);
-    NS[1] = st.s0 & ~st.s1 & ~st.s2;
-    NS[2] = st.s1 & ~st.s0;
-    NS[3] = st.s1 & st.s0;
-    NS[4] = st.s2;
-    NT[0] = ~(st.t1 | st.t2);
-    NT[1] = st.t1 ^ st.t2;
-    NT[2] = st.t1 & st.t2;
+    const uint64_t NT[3] = {st.nt0, st.nt1, st.nt2};
+    const uint64_t ns0 = bop3<kNor3>(st.s2, st.s1, st.s0);
 #pragma unroll
     for (int i = 0; i < C::n; ++i) {
         th[i] = __builtin_amdgcn_readfirstlane(thr[C::ns[i] * 3 + C::nt[i]]);
-        M[i] = NS[C::ns[i]] & NT[C::nt[i]];
+        const uint64_t nt = NT[C::nt[i]];
+        // n_s <= 4, so s0 & ~s1 means 1, s1 & ~s0 means 2, s1 & s0 means 3
+        switch (C::ns[i]) {
+            case 0: M[i] = ns0 & nt; break;
+            case 1: M[i] = bop3<kAndNotAnd>(st.s0, st.s1, nt); break;
+            case 2: M[i] = bop3<kAndNotAnd>(st.s1, st.s0, nt); break;
+            case 3: M[i] = bop3<kAnd3>(st.s1, st.s0, nt); break;
+            default: M[i] = st.s2 & nt; break;
+        }
         if (R == 3) M[i] &= ~all_if(th[i] == 0xFFFFFFFFu ? 1u : 0u, 0);
     }
 }
 
-// Three-input bitwise operation of gfx950 (v_bitop3_b32); the immediate is
-// the truth table f(0xF0, 0xCC, 0xAA) of the operand order (a, b, c).
-#define BITOP3(a, b, c, table) __builtin_amdgcn_bitop3_b32((a), (b), (c), (table))
-constexpr int kAndOr = 0xEA;      // (a & b) | c
-constexpr int kAndAndNot = 0x40;  // a & b & ~c
-constexpr int kAndXnor = 0x90;    // a & ~(b ^ c)
 
 // Level picks of the blocks q >= q0, two bytes per block, as a 256-bit
 // block-uniform shift register (see kLevelPicks).
@@ -299,27 +344,58 @@ __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, ui
     und = lo_hi(und_lo, und_hi);
 }
 
+__device__ __forceinline__ void push_word(SweepQueue& Q, uint32_t k, const WordState& st) {
+    Q.s[k] = st.s;
+    Q.w[k] = st.w;
+    Q.s0[k] = st.s0;
+    Q.s1[k] = st.s1;
+    Q.s2[k] = st.s2;
+    Q.nt0[k] = st.nt0;
+    Q.nt2[k] = st.nt2;
+    Q.acc[k] = st.acc;
+    Q.und[k] = st.und;
+}
+
+__device__ __forceinline__ WordState pop_word(const SweepQueue& Q, uint32_t k) {
+    WordState r;
+    r.s = Q.s[k];
+    r.w = Q.w[k];
+    r.s0 = Q.s0[k];
+    r.s1 = Q.s1[k];
+    r.s2 = Q.s2[k];
+    r.nt0 = Q.nt0[k];
+    r.nt2 = Q.nt2[k];
+    r.nt1 = ~(r.nt0 | r.nt2);
+    r.acc = Q.acc[k];
+    r.und = Q.und[k];
+    return r;
+}
+
 // A colour pass over the block's words: the first q_split Philox blocks of
-// levels for every word, then the words still undecided are packed into the
-// first waves of the block and finished there (far fewer waves run the long
-// tail of levels).  Every thread of the block calls this (it synchronises);
-// `valid` is false for threads past the last word.
-template <int R>
+// levels for every word; then, while the words with undecided lanes fill
+// more than one wave, they are packed into the first waves of the block and
+// given one more block; the last ones (at most one wave) are finished there.
+// Far fewer waves run the long tail of levels.  Every thread of the block
+// calls this (it synchronises); `valid` is false for threads past the last
+// word.  Packing counters: one pair per call parity (see SweepQueue); within
+// a call, round j writes counter j & 1, which round j - 1 cleared after every
+// thread had read its previous value.
+template <int R, bool kGlobal>
 __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
                                             uint32_t colour, uint32_t t, uint32_t idx, bool valid,
                                             uint32_t q_split, SweepQueue& Q, uint32_t parity) {
     using C = Classes<R>;
     const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
-    uint32_t& count = Q.count[parity & 1u];
-    if (threadIdx.x == 0) count = 0;
+    uint32_t* cnt = Q.count + 2 * (parity & 1u);
+    if (threadIdx.x == 0) {
+        cnt[0] = 0;
+        cnt[1] = 0;
+    }
     __syncthreads();
-    WordState st;
-    st.acc = 0;
-    st.und = 0;
+    uint64_t M[C::n];
+    uint32_t th[C::n];
     if (valid) {
-        st = load_word(G, S, colour, idx);
-        uint64_t M[C::n];
-        uint32_t th[C::n];
+        WordState st = load_word<kGlobal>(G, S, colour, idx);
         class_masks<R>(st, thr, M, th);
         uint64_t live = 0;
 #pragma unroll
@@ -327,54 +403,53 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
         st.acc = ~live;  // lanes outside the listed classes: dE <= 0, accepted
         st.und = live;
         compare_levels<R>(G, g, t, st.s, M, th, thr, 0, q_split, st.acc, st.und);
-    }
-    if (valid && st.und != 0) {
-        const uint32_t k = atomicAdd(&count, 1u);
-        Q.s[k] = st.s;
-        Q.w[k] = st.w;
-        Q.s0[k] = st.s0;
-        Q.s1[k] = st.s1;
-        Q.s2[k] = st.s2;
-        Q.t1[k] = st.t1;
-        Q.t2[k] = st.t2;
-        Q.acc[k] = st.acc;
-        Q.und[k] = st.und;
-    } else if (valid && st.acc) {
-        S[st.s] = st.w ^ st.acc;
+        if (st.und != 0)
+            push_word(Q, atomicAdd(&cnt[0], 1u), st);
+        else if (st.acc)
+            store64<kGlobal>(S, st.s, st.w ^ st.acc);
     }
     __syncthreads();
-    const uint32_t n = count;
-    if (threadIdx.x < n) {
-        const uint32_t k = threadIdx.x;
+    uint32_t n = __builtin_amdgcn_readfirstlane(cnt[0]);
+    uint32_t q = q_split;
+#pragma unroll 1
+    for (uint32_t j = 1; n > kWaveSize && q + 1 < 16; ++j, ++q) {
+        const bool have = threadIdx.x < n;
         WordState r;
-        r.s = Q.s[k];
-        r.w = Q.w[k];
-        r.s0 = Q.s0[k];
-        r.s1 = Q.s1[k];
-        r.s2 = Q.s2[k];
-        r.t1 = Q.t1[k];
-        r.t2 = Q.t2[k];
-        uint64_t acc = Q.acc[k], und = Q.und[k];
-        uint64_t M[C::n];
-        uint32_t th[C::n];
+        if (have) r = pop_word(Q, threadIdx.x);
+        __syncthreads();  // every entry and count read before any is rewritten
+        if (threadIdx.x == 0) cnt[(j + 1) & 1u] = 0;
+        if (have) {
+            class_masks<R>(r, thr, M, th);
+            compare_levels<R>(G, g, t, r.s, M, th, thr, q, q + 1, r.acc, r.und);
+            if (r.und != 0)
+                push_word(Q, atomicAdd(&cnt[j & 1u], 1u), r);
+            else if (r.acc)
+                store64<kGlobal>(S, r.s, r.w ^ r.acc);
+        }
+        __syncthreads();
+        n = __builtin_amdgcn_readfirstlane(cnt[j & 1u]);
+    }
+    if (threadIdx.x < n) {
+        WordState r = pop_word(Q, threadIdx.x);
         class_masks<R>(r, thr, M, th);
-        compare_levels<R>(G, g, t, r.s, M, th, thr, q_split, 16, acc, und);
-        acc |= und;  // equal on all 32 bits: r == thr, accepted
-        if (acc) S[r.s] = r.w ^ acc;
+        compare_levels<R>(G, g, t, r.s, M, th, thr, q, 16, r.acc, r.und);
+        r.acc |= r.und;  // equal on all 32 bits: r == thr, accepted
+        if (r.acc) store64<kGlobal>(S, r.s, r.w ^ r.acc);
     }
 }
 
 // S: the slot's spins (global memory, or a copy in LDS).
 // parity: alternate 0/1 between consecutive calls in one block.
+template <bool kGlobal>
 __device__ __forceinline__ void sweep_block_any(const GroupDev& G, uint64_t* S, uint32_t g,
                                                 uint32_t colour, uint32_t t, uint32_t idx,
                                                 bool valid, uint32_t q_split, SweepQueue& Q,
                                                 uint32_t parity) {
     switch (__builtin_amdgcn_readfirstlane(G.thr[g * kThrStride + 15])) {  // slot g's regime
-        case 0: sweep_block<0>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
-        case 1: sweep_block<1>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
-        case 2: sweep_block<2>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
-        default: sweep_block<3>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
+        case 0: sweep_block<0, kGlobal>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
+        case 1: sweep_block<1, kGlobal>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
+        case 2: sweep_block<2, kGlobal>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
+        default: sweep_block<3, kGlobal>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
     }
 }
 
@@ -396,7 +471,7 @@ k_half_sweep(const GroupDev G, uint32_t colour, const uint32_t* __restrict__ ctr
     const uint32_t b = xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const uint32_t g = fast_div(b, G.div_blocks);  // b / gridDim.x on the scalar unit
     const uint32_t idx = (b - g * gridDim.x) * kSweepBlock + threadIdx.x;
-    sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
+    sweep_block_any<true>(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
                     0);
 }
 
@@ -423,7 +498,7 @@ k_half_sweep_batched(const GroupDev* __restrict__ groups, const uint32_t* __rest
     const uint32_t nb = sweep_blocks_per_slot(G.V);
     const uint32_t g = fast_div(local, G.div_blocks);  // local / nb on the scalar unit
     const uint32_t idx = (local - g * nb) * kSweepBlock + threadIdx.x;
-    sweep_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
+    sweep_block_any<true>(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
                     0);
 }
 
@@ -456,7 +531,7 @@ k_chunk_fused(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ 
         for (uint32_t colour = 0; colour < 2; ++colour) {
             for (uint32_t base = 0; base < half; base += kSweepBlock) {
                 const uint32_t idx = base + threadIdx.x;
-                sweep_block_any(G, S, g, colour, t0 + it, idx, idx < half, G.q_split, Q, call++);
+                sweep_block_any<false>(G, S, g, colour, t0 + it, idx, idx < half, G.q_split, Q, call++);
             }
             __syncthreads();  // the next colour reads what this one wrote
         }
@@ -815,6 +890,23 @@ __global__ void k_philox(const uint32_t* in, uint32_t* out, uint32_t n) {
     b[3] = o.w;
 }
 
+
+// Random-number ceiling: thread i generates `blocks` Philox blocks with the
+// counters the colour pass uses (a per-thread first word, block-uniform
+// others: (i, 0, b, 0)) and stores the xor of all their output words.
+__global__ void __launch_bounds__(256)
+k_philox_probe(uint32_t* out, uint32_t n, uint32_t blocks, uint32_t k0, uint32_t k1) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t x = 0;
+#pragma unroll 1
+    for (uint32_t b = 0; b < blocks; ++b) {
+        const uint4 o = philox(make_uint4(i, 0u, b, 0u), k0, k1);
+        x ^= xor3(o.x, o.y, o.z) ^ o.w;
+    }
+    out[i] = x;
+}
+
 }  // namespace
 
 // ------------------------------- launchers ---------------------------------
@@ -860,6 +952,13 @@ hipError_t launch_zero32(void* p, size_t n, hipStream_t s) {
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, uint32_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_philox, dim3((n + 63) / 64), dim3(64), 0, s, in, out, n);
+    return hipGetLastError();
+}
+hipError_t launch_philox_probe(uint32_t* out, uint32_t n, uint32_t blocks, uint64_t key,
+                              hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox_probe, dim3((n + 255) / 256), dim3(256), 0, s, out, n, blocks,
+                       (uint32_t)key, (uint32_t)(key >> 32));
     return hipGetLastError();
 }
 hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,

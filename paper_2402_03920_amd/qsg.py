@@ -96,6 +96,7 @@ _SIGS = {
     "qsg_last_error": (C.c_char_p, [C.c_void_p]),
     "qsg_destroy": (None, [C.c_void_p]),
     "qsg_philox": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
+    "qsg_philox_probe": (C.c_int32, [C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p]),
     "qsg_mlp_param_count": (C.c_uint32, []),
     "qsg_mlp_workspace_floats": (C.c_size_t, [C.c_uint32]),
     "qsg_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
@@ -369,6 +370,15 @@ def philox_device(inputs: np.ndarray) -> np.ndarray:
                             a.shape[0], C.c_void_p(s.cuda_stream)))
     torch.cuda.synchronize()
     return d_out.cpu().numpy().view(np.uint32)
+
+
+def philox_probe(out, n_threads: int, blocks: int, key: int, stream) -> None:
+    """Enqueue the Philox throughput probe: out is an int32 device tensor of
+    n_threads words; stream a torch stream."""
+    if out.numel() < n_threads:
+        raise ValueError("output tensor too small")
+    _check(lib().qsg_philox_probe(n_threads, blocks, key, C.c_void_p(out.data_ptr()),
+                                  C.c_void_p(stream.cuda_stream)))
 
 
 # ------------------------------------------------------------- ladder MLP

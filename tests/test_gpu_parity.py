@@ -61,6 +61,24 @@ def test_gpu_philox_matches_oracle_on_random_counters():
         assert np.array_equal(out[i], chain.philox(rows[i, :4], rows[i, 4:]))
 
 
+def test_philox_probe_matches_oracle():
+    """The throughput probe computes what it claims (ragged thread count)."""
+    import torch
+    n, blocks, key = 300, 5, 0x0123456789ABCDEF
+    out = torch.zeros(n, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream()
+    qsg.philox_probe(out, n, blocks, key, s)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    k = np.array([key & 0xFFFFFFFF, key >> 32], dtype=np.uint32)
+    for i in (0, 1, 63, 64, 255, 256, 299):
+        want = 0
+        for b in range(blocks):
+            o = chain.philox(np.array([i, 0, b, 0], dtype=np.uint32), k)
+            want ^= int(o[0]) ^ int(o[1]) ^ int(o[2]) ^ int(o[3])
+        assert int(got[i]) == want, i
+
+
 def test_initial_state_matches_oracle():
     groups = small_groups()
     with qsg.Ensemble(groups, pt_every=5, swaplog_cap=32) as ens:
