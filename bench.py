@@ -82,9 +82,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--samples", type=int, default=64)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c6"],
                     help="c2 (default): 64 samples, L=16, L_tau=128; c1: one sample, L=8, "
-                         "L_tau=32; c3: 256 uneven samples; c4: L=24, L_tau=2048, 128 samples")
+                         "L_tau=32; c3: 256 uneven samples; c4: L=24, L_tau=2048, 128 samples; "
+                         "c6: the c2 shape with the paper's coupling ladder (PT over k)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default colour-pass schedule instead of tuning it per shape")
@@ -293,7 +294,8 @@ def summarize(wl, ens):
     q2 = acc[:, 160:192].mean(axis=1) / (V * V)
     return {"shape": f"L={g0.L} L_tau={g0.L_tau} N_Gamma={len(g0.gammas)}",
             "samples": len(same), "pt_steps": p,
-            "gamma": [round(float(x), 6) for x in g0.gammas],
+            "ladder": getattr(g0, "ladder", "gamma"),
+            "ladder_values": [round(float(x), 6) for x in g0.gammas],
             "space_energy_per_site": [round(float(x), 6) for x in e_sp],
             "time_energy_per_site": [round(float(x), 6) for x in e_t],
             "q2": [round(float(x), 6) for x in q2]}
@@ -305,6 +307,9 @@ def describe(wl, name):
                 f"32 Gammas geometric in [2,4], PT every {wl.pt_every} sweeps")
     if name == "c1":
         return "1 sample x 64 replicas, L=8, L_tau=32, beta=4, 16 Gammas in [1.5,4.5]"
+    if name == "c6":
+        return (f"{len(wl.groups)} samples x 64 replicas, L=16, L_tau=128, one coupling k on "
+                f"every bond, 32 k in [0.25,0.33], PT over k every {wl.pt_every} sweeps")
     if name == "c3":
         return ("256 uneven samples x 64 replicas, L in {8..24}, L_tau in {64,128,256}, "
                 "beta=L_tau/16, 24-48 Gammas in [2,4]")
@@ -327,11 +332,34 @@ def cpu_baseline(wl, n_sweeps):
     og.run(n_sweeps, 0, threads=threads)
     dt = time.perf_counter() - t0
     upd = n_sweeps * g.spin_updates_per_sweep
+    # the same oracle on one core, over a fresh copy of the sample: a sixteenth
+    # of the sweeps (at least one)
+    n1 = max(1, n_sweeps // 16)
+    og1 = chain.OracleGroup.from_workload_group(g, log_cap=8)
+    t1 = time.perf_counter()
+    og1.run(n1, 0, threads=1)
+    dt1 = time.perf_counter() - t1
+    upd1 = n1 * g.spin_updates_per_sweep
     return {"value": round(dt / upd * 1e12, 2), "unit": "ps/spin-update", "cores": threads,
             "kind": "oracle",
             "sample": f"1 of {len(wl.groups)} groups (L={g.L}, L_tau={g.L_tau}, "
                       f"{len(g.gammas)} Gammas), {n_sweeps} sweeps, no PT; {upd:.3e} "
-                      f"spin-updates in {dt:.1f} s"}
+                      f"spin-updates in {dt:.1f} s",
+            "single_core_ps_per_spin_update": round(dt1 / upd1 * 1e12, 2),
+            "single_core_sample": f"{n1} sweeps of the same sample, {upd1:.3e} spin-updates "
+                                  f"in {dt1:.1f} s",
+            "host_cpu": host_cpu(), "host_cpus_visible": cores}
+
+
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

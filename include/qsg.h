@@ -79,8 +79,19 @@ typedef struct {
     uint64_t mc_seed;        /* Philox key (lo, hi) of spins, sweeps and PT   */
     uint64_t j_seed[64];     /* Philox key of lane j's couplings              */
     uint32_t swap_table_cap; /* max swap-table entries per pair (0 = 4096)    */
-    uint32_t reserved;       /* must be 0                                     */
+    uint32_t ladder_kind;    /* QSG_LADDER_GAMMA (0) or QSG_LADDER_K (1)      */
 } qsg_group_desc;
+
+/* Ladder kinds.  GAMMA: slot g runs the two-coupling form at transverse
+ * field Gamma_g (k = beta/L_tau on space bonds, kp_g on time bonds) and PT
+ * exchanges Gamma values with the time-bond energy (qsg_set_gamma_ladder).
+ * K: the paper's own parametrisation (Sec. 1, Eqs. (2)-(3); k list of
+ * App. C): slot g has one coupling k_g on every bond (the transverse field
+ * is -ln tanh(k_g)/(2 k_g)), PT exchanges k values with the full energy,
+ * probability min(1, e^{(k_g - k_{g+1})(B[g+1]-B[g])}), B = Bsp + Bt
+ * (Sec. 2.1); set with qsg_set_k_ladder.  beta is unused (still > 0). */
+#define QSG_LADDER_GAMMA 0u
+#define QSG_LADDER_K 1u
 
 /* Run-wide settings. */
 typedef struct {
@@ -130,7 +141,8 @@ size_t qsg_workspace_bytes(const qsg_group_desc* groups, uint32_t n_groups,
 /* Create a context over `d_workspace` (device pointer, 256-byte aligned,
  * >= qsg_workspace_bytes) on HIP stream `hip_stream` (hipStream_t, may be
  * NULL for the null stream).  Builds the couplings on the device from the
- * lane seeds; the ladder is unset until qsg_set_gamma_ladder. */
+ * lane seeds; the ladder is unset until qsg_set_gamma_ladder (or
+ * qsg_set_k_ladder for QSG_LADDER_K groups). */
 qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups,
                       const qsg_run_config* cfg, void* d_workspace,
                       size_t ws_bytes, void* hip_stream, qsg_ctx** out);
@@ -138,8 +150,15 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups,
 /* Set group `group`'s ladder: n_gamma host doubles, > 0, non-decreasing.
  * Builds the Metropolis and exchange thresholds in binary128 on the host
  * and uploads them.  QSG_E_UNSUPPORTED if an exchange table would exceed
- * swap_table_cap. */
+ * swap_table_cap; QSG_E_INVALID for a group of ladder_kind QSG_LADDER_K. */
 qsg_status qsg_set_gamma_ladder(qsg_ctx* ctx, uint32_t group, const double* gamma);
+
+/* The same for a group of ladder_kind QSG_LADDER_K: n_gamma couplings k_g,
+ * > 0, non-increasing (the paper's decreasing k list, App. C; slot 0 has
+ * the largest k, i.e. the smallest transverse field).  Metropolis dE =
+ * 4 k_g (3 - n_s - n_t); exchange thresholds from e^{-4 m (k_g - k_{g+1})}
+ * for B[g+1] - B[g] = -4m with B = Bsp + Bt. */
+qsg_status qsg_set_k_ladder(qsg_ctx* ctx, uint32_t group, const double* k);
 
 /* Random initial spins (Philox counter (site, 0, 2<<24 | g, group_id)) for
  * every group; resets sweep/PT counters, walkers, round trips, sums. */
@@ -180,6 +199,11 @@ qsg_status qsg_get_tables(qsg_ctx* ctx, uint32_t group, uint32_t* thr,
 qsg_status qsg_build_tables(double beta, uint32_t L_tau, uint32_t n_gamma,
                             const double* gamma, uint32_t cap, uint32_t* thr,
                             uint8_t* swap_equal, uint32_t* swap_len, uint32_t* swap_thr);
+
+/* Host-only table builder for a coupling ladder: same arithmetic as
+ * qsg_set_k_ladder, same output layout as qsg_build_tables. */
+qsg_status qsg_build_tables_k(uint32_t n_gamma, const double* k, uint32_t cap, uint32_t* thr,
+                              uint8_t* swap_equal, uint32_t* swap_len, uint32_t* swap_thr);
 
 /* Colour-pass schedule of one group (the autotuner's knob): Philox blocks
  * every word goes through before the words still undecided are packed into

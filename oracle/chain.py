@@ -113,7 +113,7 @@ class _State(C.Structure):
         ("swaplog", C.c_void_p), ("log_cap", C.c_uint64),
         ("sum_Bsp", C.c_void_p), ("sum_Bt", C.c_void_p), ("sum_q", C.c_void_p),
         ("sum_q2", C.c_void_p), ("counters", C.c_void_p), ("hist", C.c_void_p),
-        ("slot_base", C.c_uint32),
+        ("slot_base", C.c_uint32), ("exch_all", C.c_uint32),
     ]
 
 
@@ -125,7 +125,13 @@ class OracleGroup:
     """
 
     def __init__(self, L, L_tau, beta, gammas, group_id, mc_seed, j_seeds,
-                 log_cap=4096, thr=None, swap=None, spins=None, slot_base=0):
+                 log_cap=4096, thr=None, swap=None, spins=None, slot_base=0,
+                 ladder="gamma"):
+        """`gammas` is the ladder: transverse fields (ascending) for
+        ladder="gamma", couplings k_g (descending) for ladder="k"."""
+        if ladder not in ("gamma", "k"):
+            raise ValueError("ladder must be 'gamma' or 'k'")
+        self.ladder = ladder
         self.L, self.L_tau, self.beta = int(L), int(L_tau), float(beta)
         self.gammas = np.asarray(gammas, dtype=np.float64)
         self.N = len(self.gammas)
@@ -133,11 +139,14 @@ class OracleGroup:
         self.j_seeds = [int(s) for s in j_seeds]
         N, V = self.N, self.L * self.L * self.L_tau
         self.V = V
-        self.thr = np.ascontiguousarray(
-            tables.metropolis_thresholds(beta, L_tau, self.gammas)
-            if thr is None else thr, dtype=np.uint32).reshape(N, 15)
-        eq, ln, off, flat = (tables.flat_swap_tables(beta, L_tau, self.gammas)
-                             if swap is None else swap)
+        if thr is None:
+            thr = (tables.metropolis_thresholds_k(self.gammas) if ladder == "k"
+                   else tables.metropolis_thresholds(beta, L_tau, self.gammas))
+        self.thr = np.ascontiguousarray(thr, dtype=np.uint32).reshape(N, 15)
+        if swap is None:
+            swap = (tables.flat_swap_tables_k(self.gammas) if ladder == "k"
+                    else tables.flat_swap_tables(beta, L_tau, self.gammas))
+        eq, ln, off, flat = swap
         self.pt_equal = np.ascontiguousarray(eq, dtype=np.uint8)
         self.sw_len = np.ascontiguousarray(ln, dtype=np.uint32)
         self.sw_off = np.ascontiguousarray(off, dtype=np.uint64)
@@ -178,19 +187,20 @@ class OracleGroup:
             _p(self.Bsp), _p(self.Bt), _p(self.walker), _p(self.rt_state),
             _p(self.rt_tlast), _p(self.rt_count), _p(self.rt_sum), _p(self.acc),
             _p(self.swaplog), self.log_cap, _p(self.sum_Bsp), _p(self.sum_Bt),
-            _p(self.sum_q), _p(self.sum_q2), _p(self.counters), _p(self.hist), self.slot_base)
+            _p(self.sum_q), _p(self.sum_q2), _p(self.counters), _p(self.hist), self.slot_base,
+            1 if ladder == "k" else 0)
 
     @classmethod
     def from_workload_group(cls, grp, **kw):
         return cls(grp.L, grp.L_tau, grp.beta, grp.gammas, grp.group_id,
-                   grp.mc_seed, grp.j_seeds, **kw)
+                   grp.mc_seed, grp.j_seeds, ladder=grp.ladder, **kw)
 
     @classmethod
     def single_slot(cls, grp, g, **kw):
         """Slot g of a group on its own (valid between PT steps, where the
         slots of a group evolve independently)."""
         return cls(grp.L, grp.L_tau, grp.beta, [grp.gammas[g]], grp.group_id,
-                   grp.mc_seed, grp.j_seeds, slot_base=g, **kw)
+                   grp.mc_seed, grp.j_seeds, slot_base=g, ladder=grp.ladder, **kw)
 
     # ------------------------------------------------------------------
     @property

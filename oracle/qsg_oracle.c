@@ -9,9 +9,13 @@
  *
  * Model (paper: Sec. 1, Eqs. (1)-(3), Trotter-Suzuki map to an
  * L x L x L_tau prism; Sec. 2.1, checkerboard Metropolis and parallel
- * tempering).  Two-coupling form: spatial bonds carry k*J with
- * k = beta/L_tau, temporal bonds carry kp_g = -1/2 ln tanh(beta*Gamma_g/L_tau);
- * the paper's equal-coupling form is the case kp = k.
+ * tempering).  Two ladders.  Transverse-field ladder (two-coupling form):
+ * spatial bonds carry k*J with k = beta/L_tau, temporal bonds carry
+ * kp_g = -1/2 ln tanh(beta*Gamma_g/L_tau), and PT exchanges Gamma values with
+ * the time-bond energy.  Coupling ladder (the paper's own form): one
+ * coupling k_g on every bond of slot g, PT exchanges k values with the whole
+ * energy.  The tables (built by the caller) carry the couplings; the chain
+ * only needs to know which energy the exchange uses.
  *
  * Conventions (readings of the paper, listed in the design notes):
  *  - spins: uint64 word per (slot g, tau, y, x); bit j = lane j; bit 1 <=> S = -1
@@ -304,6 +308,10 @@ typedef struct {
                                 full ladder (random-number counters only); lets a
                                 test follow a few slots of a large group between
                                 PT steps, where slots evolve independently     */
+    uint32_t exch_all;       /* 0: the slots differ in the time coupling only
+                                (transverse-field ladder), the exchange uses Bt;
+                                1: one coupling k_g on every bond (k ladder), the
+                                exchange uses the whole energy Bsp + Bt        */
 } oracle_state;
 
 static void pt_step(oracle_state *st, int *failed) {
@@ -339,13 +347,17 @@ static void pt_step(oracle_state *st, int *failed) {
     }
 
     /* Pairs in ascending order; each decision sees the state left by the
-     * previous one.  Swap probability min(1, e^{(kp_g - kp_{g+1}) D}) with
-     * D = Bt[g+1] - Bt[g] (Sec. 2.1, the exchange probability, written for
-     * the temporal coupling that differs between slots). */
+     * previous one.  Swap probability min(1, e^{(c_g - c_{g+1}) D}) (Sec. 2.1,
+     * the exchange probability): for a transverse-field ladder c = kp, the
+     * coupling that differs between slots, and D = Bt[g+1] - Bt[g]; for a k
+     * ladder c = k and D is the change of the whole exponent Bsp + Bt
+     * (Eq. (3)). */
     for (int g = 0; g + 1 < N; ++g) {
         uint64_t mask = 0;
         for (int j = 0; j < 64; ++j) {
             int64_t D = (int64_t)st->Bt[(g + 1) * 64 + j] - st->Bt[g * 64 + j];
+            if (st->exch_all)
+                D += (int64_t)st->Bsp[(g + 1) * 64 + j] - st->Bsp[g * 64 + j];
             int accept;
             if (st->pt_equal[g] || D >= 0) {
                 accept = 1;

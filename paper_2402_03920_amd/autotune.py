@@ -27,6 +27,9 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedu
 
 
 def shape_key(g) -> str:
+    if getattr(g, "ladder", "gamma") == "k":
+        return (f"L{g.L}_Lt{g.L_tau}_N{len(g.gammas)}_"
+                f"K{float(g.gammas[0]):.6g}-{float(g.gammas[-1]):.6g}")
     return (f"L{g.L}_Lt{g.L_tau}_N{len(g.gammas)}_b{float(g.beta):.6g}_"
             f"G{float(g.gammas[0]):.6g}-{float(g.gammas[-1]):.6g}")
 

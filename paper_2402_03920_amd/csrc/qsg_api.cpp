@@ -22,6 +22,9 @@
 extern "C" int qsg_tables_build_host(double beta, uint32_t L_tau, uint32_t N, const double* gamma,
                                      uint32_t cap, uint32_t* thr, uint8_t* eq, uint32_t* len,
                                      uint32_t* sw, char* err, size_t errlen);
+extern "C" int qsg_tables_build_host_k(uint32_t N, const double* k, uint32_t cap, uint32_t* thr,
+                                       uint8_t* eq, uint32_t* len, uint32_t* sw, char* err,
+                                       size_t errlen);
 
 namespace {
 
@@ -68,8 +71,8 @@ bool valid_desc(const qsg_group_desc& d, std::string* why) {
         std::snprintf(buf, sizeof buf, "n_gamma=%u must be in [1, %d]", d.n_gamma, QSG_MAX_GAMMA);
     } else if ((uint64_t)d.L * d.L * d.L_tau > (1ull << 31)) {
         std::snprintf(buf, sizeof buf, "L*L*L_tau too large");
-    } else if (d.reserved != 0) {
-        std::snprintf(buf, sizeof buf, "reserved field must be 0");
+    } else if (d.ladder_kind != QSG_LADDER_GAMMA && d.ladder_kind != QSG_LADDER_K) {
+        std::snprintf(buf, sizeof buf, "ladder_kind=%u unknown", d.ladder_kind);
     } else if (swap_cap_of(d) > (1u << 24)) {
         std::snprintf(buf, sizeof buf, "swap_table_cap too large");
     } else {
@@ -347,6 +350,49 @@ void for_state_regions(const qsg_ctx* c, F f) {
 }
 }  // namespace
 
+namespace {
+// Build a group's tables with the host builder of its ladder kind and upload
+// them (thresholds, regime, level picks, exchange tables).
+qsg_status set_ladder(qsg_ctx* c, uint32_t group, const double* values, uint32_t kind) {
+    if (qsg_status st = check_ctx(c)) return st;
+    if (group >= c->desc.size()) return fail(c, QSG_E_INVALID, "group %u out of range", group);
+    if (!values) return fail(c, QSG_E_INVALID, "ladder is null");
+    const qsg_group_desc& d = c->desc[group];
+    if (d.ladder_kind != kind)
+        return fail(c, QSG_E_INVALID, "group %u has ladder kind %u", group, d.ladder_kind);
+    const GroupDev& g = c->gd[group];
+    const uint32_t N = d.n_gamma, pairs = N > 1 ? N - 1 : 1;
+    std::vector<uint32_t> thr15(N * 15), thr(N * qsg::kThrStride, 0), len(pairs, 0),
+        sw((size_t)pairs * g.sw_cap, 0), eq32(pairs, 0);
+    std::vector<uint8_t> eq(pairs, 0);
+    char err[256] = {0};
+    int rc = kind == QSG_LADDER_K
+                 ? qsg_tables_build_host_k(N, values, g.sw_cap, thr15.data(), eq.data(), len.data(),
+                                           sw.data(), err, sizeof err)
+                 : qsg_tables_build_host(d.beta, d.L_tau, N, values, g.sw_cap, thr15.data(),
+                                         eq.data(), len.data(), sw.data(), err, sizeof err);
+    if (rc == -1) return fail(c, QSG_E_INVALID, "%s", err);
+    if (rc != 0) return fail(c, QSG_E_UNSUPPORTED, "%s", err);
+    for (uint32_t i = 0; i < N; ++i) {
+        for (int k = 0; k < 15; ++k) thr[i * qsg::kThrStride + k] = thr15[i * 15 + k];
+        const uint32_t r = class_regime(&thr15[i * 15]);
+        thr[i * qsg::kThrStride + 15] = r;
+        level_picks(&thr15[i * 15], r, &thr[i * qsg::kThrStride + qsg::kLevelPicks]);
+    }
+    for (uint32_t i = 0; i < pairs; ++i) eq32[i] = eq[i];
+    hipStream_t s = c->stream;
+    QSG_HIP(c, hipMemcpyAsync(g.thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice, s));
+    QSG_HIP(c, hipMemcpyAsync(g.sw_thr, sw.data(), sw.size() * 4, hipMemcpyHostToDevice, s));
+    QSG_HIP(c, hipMemcpyAsync(g.sw_len, len.data(), len.size() * 4, hipMemcpyHostToDevice, s));
+    QSG_HIP(c, hipMemcpyAsync(g.sw_eq, eq32.data(), eq32.size() * 4, hipMemcpyHostToDevice, s));
+    QSG_HIP(c, hipStreamSynchronize(s));
+    c->ladder[group].assign(values, values + N);
+    c->ladder_set[group] = true;
+    return QSG_OK;
+}
+
+}  // namespace
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -410,6 +456,7 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         g.sw_cap = swap_cap_of(d);
         g.log_cap = cfg->swaplog_cap;
         g.q_split = cfg->sweep_split ? (cfg->sweep_split > 16 ? 16 : cfg->sweep_split) : 4;
+        g.exch_all = d.ladder_kind == QSG_LADDER_K ? 1u : 0u;
         g.spins = at<uint64_t>(c, gl.spins);
         g.Jx = at<uint64_t>(c, gl.Jx);
         g.Jy = at<uint64_t>(c, gl.Jy);
@@ -482,36 +529,11 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
 }
 
 qsg_status qsg_set_gamma_ladder(qsg_ctx* c, uint32_t group, const double* gamma) {
-    if (qsg_status st = check_ctx(c)) return st;
-    if (group >= c->desc.size()) return fail(c, QSG_E_INVALID, "group %u out of range", group);
-    if (!gamma) return fail(c, QSG_E_INVALID, "gamma is null");
-    const qsg_group_desc& d = c->desc[group];
-    const GroupDev& g = c->gd[group];
-    const uint32_t N = d.n_gamma, pairs = N > 1 ? N - 1 : 1;
-    std::vector<uint32_t> thr15(N * 15), thr(N * qsg::kThrStride, 0), len(pairs, 0),
-        sw((size_t)pairs * g.sw_cap, 0), eq32(pairs, 0);
-    std::vector<uint8_t> eq(pairs, 0);
-    char err[256] = {0};
-    int rc = qsg_tables_build_host(d.beta, d.L_tau, N, gamma, g.sw_cap, thr15.data(), eq.data(),
-                                   len.data(), sw.data(), err, sizeof err);
-    if (rc == -1) return fail(c, QSG_E_INVALID, "%s", err);
-    if (rc != 0) return fail(c, QSG_E_UNSUPPORTED, "%s", err);
-    for (uint32_t i = 0; i < N; ++i) {
-        for (int k = 0; k < 15; ++k) thr[i * qsg::kThrStride + k] = thr15[i * 15 + k];
-        const uint32_t r = class_regime(&thr15[i * 15]);
-        thr[i * qsg::kThrStride + 15] = r;
-        level_picks(&thr15[i * 15], r, &thr[i * qsg::kThrStride + qsg::kLevelPicks]);
-    }
-    for (uint32_t i = 0; i < pairs; ++i) eq32[i] = eq[i];
-    hipStream_t s = c->stream;
-    QSG_HIP(c, hipMemcpyAsync(g.thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice, s));
-    QSG_HIP(c, hipMemcpyAsync(g.sw_thr, sw.data(), sw.size() * 4, hipMemcpyHostToDevice, s));
-    QSG_HIP(c, hipMemcpyAsync(g.sw_len, len.data(), len.size() * 4, hipMemcpyHostToDevice, s));
-    QSG_HIP(c, hipMemcpyAsync(g.sw_eq, eq32.data(), eq32.size() * 4, hipMemcpyHostToDevice, s));
-    QSG_HIP(c, hipStreamSynchronize(s));
-    c->ladder[group].assign(gamma, gamma + N);
-    c->ladder_set[group] = true;
-    return QSG_OK;
+    return set_ladder(c, group, gamma, QSG_LADDER_GAMMA);
+}
+
+qsg_status qsg_set_k_ladder(qsg_ctx* c, uint32_t group, const double* k) {
+    return set_ladder(c, group, k, QSG_LADDER_K);
 }
 
 qsg_status qsg_init_spins(qsg_ctx* c) {
@@ -827,6 +849,18 @@ qsg_status qsg_build_tables(double beta, uint32_t L_tau, uint32_t n_gamma, const
     char err[256] = {0};
     int rc = qsg_tables_build_host(beta, L_tau, n_gamma, gamma, cap, thr, swap_equal, swap_len,
                                    swap_thr, err, sizeof err);
+    if (rc == -1) return fail(nullptr, QSG_E_INVALID, "%s", err);
+    if (rc != 0) return fail(nullptr, QSG_E_UNSUPPORTED, "%s", err);
+    return QSG_OK;
+}
+
+qsg_status qsg_build_tables_k(uint32_t n_gamma, const double* k, uint32_t cap, uint32_t* thr,
+                              uint8_t* swap_equal, uint32_t* swap_len, uint32_t* swap_thr) {
+    if (n_gamma == 0 || n_gamma > QSG_MAX_GAMMA || !k || cap == 0)
+        return fail(nullptr, QSG_E_INVALID, "bad n_gamma, k or cap");
+    char err[256] = {0};
+    int rc = qsg_tables_build_host_k(n_gamma, k, cap, thr, swap_equal, swap_len, swap_thr, err,
+                                     sizeof err);
     if (rc == -1) return fail(nullptr, QSG_E_INVALID, "%s", err);
     if (rc != 0) return fail(nullptr, QSG_E_UNSUPPORTED, "%s", err);
     return QSG_OK;

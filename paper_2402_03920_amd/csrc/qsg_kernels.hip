@@ -706,7 +706,7 @@ __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
         const int32_t nx_sp = G.E[((g + 1) * 64 + j) * 2 + 0];
         const int32_t nx_t = G.E[((g + 1) * 64 + j) * 2 + 1];
         const uint32_t nx_w = G.walker[(g + 1) * 64 + j];
-        const int32_t D = nx_t - cur_t;
+        const int32_t D = G.exch_all ? (nx_sp + nx_t) - (cur_sp + cur_t) : nx_t - cur_t;
         bool accept;
         if (G.sw_eq[g] || D >= 0) {
             accept = true;

@@ -50,7 +50,7 @@ class qsg_group_desc(C.Structure):
     _fields_ = [("L", C.c_uint32), ("L_tau", C.c_uint32), ("beta", C.c_double),
                 ("n_gamma", C.c_uint32), ("group_id", C.c_uint32),
                 ("mc_seed", C.c_uint64), ("j_seed", C.c_uint64 * 64),
-                ("swap_table_cap", C.c_uint32), ("reserved", C.c_uint32)]
+                ("swap_table_cap", C.c_uint32), ("ladder_kind", C.c_uint32)]
 
 
 class qsg_run_config(C.Structure):
@@ -75,6 +75,7 @@ _SIGS = {
     "qsg_create": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t,
                                C.c_void_p, C.POINTER(C.c_void_p)]),
     "qsg_set_gamma_ladder": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p]),
+    "qsg_set_k_ladder": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p]),
     "qsg_init_spins": (C.c_int32, [C.c_void_p]),
     "qsg_sweep": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32]),
     "qsg_pt_swap": (C.c_int32, [C.c_void_p]),
@@ -90,6 +91,8 @@ _SIGS = {
     "qsg_build_tables": (C.c_int32, [C.c_double, C.c_uint32, C.c_uint32, C.c_void_p,
                                      C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p]),
+    "qsg_build_tables_k": (C.c_int32, [C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]),
     "qsg_set_deadline": (C.c_int32, [C.c_void_p, C.c_double]),
     "qsg_set_schedule": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32]),
     "qsg_sync": (C.c_int32, [C.c_void_p]),
@@ -156,8 +159,24 @@ def qsg_build_tables(beta: float, L_tau: int, gammas: Sequence[float], cap: int 
     return thr.reshape(N, 15), eq[:N - 1], ln[:N - 1], sw.reshape(pairs, cap)[:N - 1]
 
 
+def qsg_build_tables_k(ks: Sequence[float], cap: int = 4096):
+    """Host table builder of a coupling ladder, same outputs as qsg_build_tables."""
+    k = np.ascontiguousarray(np.asarray(ks, dtype=np.float64))
+    N = k.size
+    pairs = max(N - 1, 1)
+    thr = np.zeros(N * 15, np.uint32)
+    eq = np.zeros(pairs, np.uint8)
+    ln = np.zeros(pairs, np.uint32)
+    sw = np.zeros(pairs * cap, np.uint32)
+    _check(lib().qsg_build_tables_k(N, _ptr(k), cap, _ptr(thr), _ptr(eq), _ptr(ln), _ptr(sw)))
+    return thr.reshape(N, 15), eq[:N - 1], ln[:N - 1], sw.reshape(pairs, cap)[:N - 1]
+
+
+LADDER_KINDS = {"gamma": 0, "k": 1}
+
+
 def make_desc(L, L_tau, beta, n_gamma, group_id, mc_seed, j_seeds,
-              swap_table_cap=0) -> qsg_group_desc:
+              swap_table_cap=0, ladder="gamma") -> qsg_group_desc:
     d = qsg_group_desc()
     d.L, d.L_tau, d.beta = int(L), int(L_tau), float(beta)
     d.n_gamma, d.group_id, d.mc_seed = int(n_gamma), int(group_id), int(mc_seed)
@@ -167,7 +186,7 @@ def make_desc(L, L_tau, beta, n_gamma, group_id, mc_seed, j_seeds,
     for j, s in enumerate(seeds):
         d.j_seed[j] = int(s)
     d.swap_table_cap = int(swap_table_cap)
-    d.reserved = 0
+    d.ladder_kind = LADDER_KINDS[ladder]
     return d
 
 
@@ -175,7 +194,7 @@ class Ensemble:
     """A set of groups on the current CUDA (HIP) device and stream.
 
     `groups` are objects with L, L_tau, beta, gammas, group_id, mc_seed,
-    j_seeds (e.g. qsg_workloads.Group).
+    j_seeds and optionally ladder ("gamma" or "k"; e.g. qsg_workloads.Group).
     """
 
     def __init__(self, groups: Sequence, pt_every: int = 10, swaplog_cap: int = 1024,
@@ -188,7 +207,8 @@ class Ensemble:
         self.descs = (qsg_group_desc * self.n)()
         for i, g in enumerate(self.groups):
             self.descs[i] = make_desc(g.L, g.L_tau, g.beta, len(g.gammas), g.group_id,
-                                      g.mc_seed, g.j_seeds, swap_table_cap)
+                                      g.mc_seed, g.j_seeds, swap_table_cap,
+                                      getattr(g, "ladder", "gamma"))
         self.cfg = qsg_run_config(int(pt_every), int(swaplog_cap), int(sweep_split), 0)
         nbytes = L_.qsg_workspace_bytes(self.descs, self.n, C.byref(self.cfg))
         if nbytes == 0:
@@ -203,7 +223,10 @@ class Ensemble:
                              C.c_void_p(self.workspace.data_ptr()), nbytes,
                              C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx)))
         for i, g in enumerate(self.groups):
-            self.set_gamma_ladder(i, g.gammas)
+            if getattr(g, "ladder", "gamma") == "k":
+                self.set_k_ladder(i, g.gammas)
+            else:
+                self.set_gamma_ladder(i, g.gammas)
 
     # -- lifecycle
     def close(self):
@@ -229,6 +252,12 @@ class Ensemble:
         if g.size != self.descs[i].n_gamma:
             raise ValueError("ladder length differs from n_gamma")
         _check(lib().qsg_set_gamma_ladder(self.ctx, i, _ptr(g)), self.ctx)
+
+    def set_k_ladder(self, i: int, ks):
+        k = np.ascontiguousarray(np.asarray(ks, dtype=np.float64))
+        if k.size != self.descs[i].n_gamma:
+            raise ValueError("ladder length differs from n_gamma")
+        _check(lib().qsg_set_k_ladder(self.ctx, i, _ptr(k)), self.ctx)
 
     def init_spins(self):
         _check(lib().qsg_init_spins(self.ctx), self.ctx)

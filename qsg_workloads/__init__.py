@@ -45,7 +45,9 @@ class Group:
 
     j_seeds has 64 entries (one per lane).  All equal means one disorder
     sample with 64 replicas; distinct values put a different sample in
-    every lane.
+    every lane.  `gammas` is the ladder: transverse fields, ascending, for
+    ladder == "gamma"; couplings k_g, descending, for ladder == "k" (the
+    paper's own PT variable; beta is then unused).
     """
 
     L: int
@@ -55,6 +57,7 @@ class Group:
     group_id: int
     mc_seed: int
     j_seeds: List[int]
+    ladder: str = "gamma"
 
     @property
     def n_gamma(self) -> int:
@@ -156,6 +159,33 @@ def c5_eval(ladders: Sequence[np.ndarray] | None = None,
     return Workload("learned-ladder eval", groups, 10_000, 10)
 
 
+def linear_k_ladder(kmax: float, kmin: float, n: int) -> np.ndarray:
+    """n couplings from kmax down to kmin, equally spaced (descending)."""
+    if n == 1:
+        return np.array([float(kmax)])
+    lad = np.linspace(float(kmax), float(kmin), n)
+    lad[0], lad[-1] = kmax, kmin
+    return np.minimum.accumulate(lad)
+
+
+def c6_coupling_ladder(n_samples: int = 64) -> Workload:
+    """The paper's own parametrisation (one coupling k on every bond, PT over
+    k): 64 samples (64 replicas each), L=16, L_tau=128, 32 couplings from
+    0.33 down to 0.25 around the paper's k ~ 0.29, J seeds 1..64, 10^4
+    sweeps, PT every 10.  beta is unused by this form (set to 1)."""
+    lad = linear_k_ladder(0.33, 0.25, 32)
+    groups = [Group(16, 128, 1.0, lad, i, MC_SEED, _replicas(i + 1), ladder="k")
+              for i in range(n_samples)]
+    return Workload("k ladder L=16 Ltau=128 NK=32 64 samples", groups, 10_000, 10)
+
+
+def tiny_k_group(L=4, L_tau=8, n_k=3, kmax=0.5, kmin=0.2, group_id=0, mc_seed=MC_SEED,
+                 j_seed=1, per_lane=False) -> Group:
+    seeds = [j_seed + j for j in range(64)] if per_lane else _replicas(j_seed)
+    return Group(L, L_tau, 1.0, linear_k_ladder(kmax, kmin, n_k), group_id, mc_seed, seeds,
+                 ladder="k")
+
+
 def tiny_group(L=4, L_tau=8, beta=1.0, n_gamma=3, gmin=0.5, gmax=2.0,
                group_id=0, mc_seed=MC_SEED, j_seed=1, per_lane=False) -> Group:
     lad = geometric_ladder(gmin, gmax, n_gamma)
@@ -169,4 +199,5 @@ ALL = {
     "c3": c3_batched_uneven,
     "c4": c4_production,
     "c5": c5_eval,
+    "c6": c6_coupling_ladder,
 }

@@ -105,3 +105,42 @@ def test_binary128_tables_equal_oracle_mpmath(case):
     for g, t in enumerate(otabs):
         assert np.array_equal(sw[g, :len(t)], t)
         assert np.all(sw[g, len(t):] == 0)
+
+
+def test_ladder_kind_is_validated():
+    assert _ws_bytes(_desc(ladder="k")) > 0
+    d = _desc()
+    d.ladder_kind = 2
+    assert _ws_bytes(d) == 0
+
+
+def test_host_k_tables_reject_bad_ladders():
+    for bad in ([0.2, 0.3], [0.3, -0.1], [0.3, float("nan")]):
+        with pytest.raises(qsg.QSGError) as e:
+            qsg.qsg_build_tables_k(bad)
+        assert e.value.code == qsg.QSG_E_INVALID, bad
+    with pytest.raises(qsg.QSGError) as e:
+        qsg.qsg_build_tables_k([0.3, 0.3 - 1e-9], cap=64)
+    assert e.value.code == qsg.QSG_E_UNSUPPORTED
+
+
+def _k_ladders():
+    return [W.c6_coupling_ladder(1).groups[0].gammas,            # 32 k in [0.25, 0.33]
+            W.linear_k_ladder(0.5, 0.2, 3),
+            np.array([0.4, 0.4, 0.3, 0.05]),                       # equal pair
+            np.array([2.5, 1e-3])]                                 # saturated and tiny k
+
+
+@pytest.mark.parametrize("case", range(len(_k_ladders())))
+def test_binary128_k_tables_equal_oracle_mpmath(case):
+    lad = _k_ladders()[case]
+    cap = 8192
+    thr, eq, ln, sw = qsg.qsg_build_tables_k(lad, cap=cap)
+    othr = tables.metropolis_thresholds_k(lad).reshape(len(lad), 15)
+    assert np.array_equal(thr, othr)
+    oeq, oln, otabs = tables.swap_tables_k(lad)
+    assert np.array_equal(eq, oeq)
+    assert np.array_equal(ln, oln)
+    for g, t in enumerate(otabs):
+        assert np.array_equal(sw[g, :len(t)], t)
+        assert np.all(sw[g, len(t):] == 0)

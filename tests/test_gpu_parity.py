@@ -108,6 +108,49 @@ def test_small_groups_bit_exact(mode):
             compare_state(ens, ogs)
 
 
+def k_groups():
+    return [
+        W.tiny_k_group(L=4, L_tau=8, n_k=4, kmax=0.6, kmin=0.25, group_id=10),
+        W.tiny_k_group(L=6, L_tau=4, n_k=3, kmax=0.45, kmin=0.3, group_id=11, per_lane=True,
+                       j_seed=300),
+        W.tiny_k_group(L=12, L_tau=10, n_k=5, kmax=0.35, kmin=0.27, group_id=12, j_seed=9),
+    ]
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_k_ladder_groups_bit_exact(mode):
+    """Coupling-ladder groups (one k on every bond, exchange on the full
+    energy) next to transverse-field groups in the same launches."""
+    groups = k_groups() + small_groups()[:2]
+    say(f"[parity] k-ladder groups, mode={mode}")
+    ogs = oracle_groups(groups, 32)
+    with qsg.Ensemble(groups, pt_every=5, swaplog_cap=32) as ens:
+        ens.init_spins()
+        for i, g in enumerate(groups):
+            thr, eq, ln, sw = ens.get_tables(i)
+            assert np.array_equal(thr, ogs[i].thr)
+        for n in (7, 13, 20):
+            ens.sweep(n, MODES[mode])
+            for og in ogs:
+                og.run(n, 5)
+            compare_state(ens, ogs)
+        assert all(int(og.acc.sum()) > 0 for og in ogs[:3])
+
+
+def test_k_ladder_workload_truncated_bit_exact():
+    """Two samples of the k-ladder workload (L=16, L_tau=128, 32 k in
+    [0.25, 0.33]), 20 sweeps with PT every 10."""
+    wl = W.c6_coupling_ladder(n_samples=2)
+    ogs = oracle_groups(wl.groups, 16)
+    say("[parity] k-ladder workload oracle")
+    for og in ogs:
+        og.run(20, 10, threads=16)
+    with qsg.Ensemble(wl.groups, pt_every=10, swaplog_cap=16) as ens:
+        ens.init_spins()
+        ens.sweep(20, qsg.QSG_BATCHED | qsg.QSG_GRAPH)
+        compare_state(ens, ogs)
+
+
 def test_explicit_pt_step_and_no_pt_flag():
     groups = small_groups()[:4]
     ogs = oracle_groups(groups, 16)

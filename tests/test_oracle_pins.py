@@ -378,3 +378,94 @@ def test_pt_marginals_match_transfer_matrix():
         _check_mean(acc_t[g], tm["Bt"])
         _check_mean(acc_sp[g], tm["Bsp"])
     assert og.acc.sum() > 0
+
+
+# ------------------------------------------------------------------------
+# Coupling ladder (one k on every bond, PT over k: the paper's Sec. 1
+# parametrisation and Sec. 2.1 exchange with the full energy).
+
+def test_k_ladder_thresholds_are_the_two_coupling_form_at_the_dual_field():
+    """With beta/L_tau = k, the paper's relation Gamma = -ln tanh(k)/(2k)
+    (Sec. 1) makes the time coupling -1/2 ln tanh(beta Gamma/L_tau) equal to
+    k (the duality tanh(a) = e^{-2b} <=> tanh(b) = e^{-2a}), so each slot of
+    a k ladder must have exactly the transverse-field table of that point;
+    only three energy levels 4k, 8k, 12k occur (App. B's daemon levels)."""
+    ks = W.linear_k_ladder(0.45, 0.2, 6)
+    L_tau = 64
+    thr_k = tables.metropolis_thresholds_k(ks)
+    for g, k in enumerate(ks):
+        gam = tables.gamma_of_equal_coupling(float(k))
+        thr_g = tables.metropolis_thresholds(float(k) * L_tau, L_tau, [gam])[0]
+        assert np.array_equal(thr_k[g], thr_g), g
+        levels = sorted(set(int(x) for x in thr_k[g].reshape(-1)) - {2 ** 32 - 1})
+        assert len(levels) == 3
+
+
+def test_k_ladder_swap_frequency_uses_the_whole_energy():
+    """Two k slots started with known Bsp and Bt: the first PT step accepts
+    with frequency e^{(k_0-k_1) D}, D the change of Bsp + Bt (an exchange
+    on Bt alone would give a visibly different rate)."""
+    L, L_tau = 4, 8
+    ks = [0.40, 0.34]
+    V = L * L * L_tau
+    s0 = np.zeros(V, dtype=np.uint64)
+    s1 = np.zeros((L_tau, L * L), dtype=np.uint64)
+    s1[1::2, 0] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    spins = np.concatenate([s0, s1.reshape(-1)])
+    accepted = trials = 0
+    D_all = D_t = None
+    for rep in range(60):
+        og = chain.OracleGroup(L, L_tau, 1.0, ks, rep, 42, [3] * 64, spins=spins, ladder="k")
+        bsp = og.Bsp.reshape(2, 64)
+        bt = og.Bt.reshape(2, 64)
+        D = (bsp[1] + bt[1]) - (bsp[0] + bt[0])
+        assert np.all(D == D[0])
+        D_all, D_t = int(D[0]), int(bt[1][0] - bt[0][0])
+        og.pt_step()
+        accepted += bin(int(og.swaplog_rows()[0][0])).count("1")
+        trials += 64
+    assert D_all < 0 and D_all != D_t
+    p_all = math.exp((ks[0] - ks[1]) * D_all)
+    p_t = math.exp((ks[0] - ks[1]) * D_t)
+    f = accepted / trials
+    err = math.sqrt(p_all * (1 - p_all) / trials)
+    assert abs(f - p_all) < 5 * err
+    assert abs(f - p_t) > 5 * err
+
+
+@pytest.mark.slow
+def test_k_ladder_pt_marginals_match_transfer_matrix():
+    """Three k slots on L=2, L_tau=32: with exchanges on the full energy each
+    slot still samples its own Boltzmann weight e^{k_g (Bsp + Bt)} (exact
+    per-slot averages from the transfer matrix at k = kp = k_g)."""
+    L, L_tau = 2, 32
+    ks = [0.55, 0.42, 0.30]
+    _, _, jx, jy = _lane0_couplings(L, 11)
+    og = chain.OracleGroup(L, L_tau, 1.0, ks, 0, 42, [11] * 64, ladder="k")
+    og.run(200, 2)
+    n = 1500
+    acc_t = np.zeros((3, 64))
+    acc_sp = np.zeros((3, 64))
+    for _ in range(n):
+        og.run(2, 2)
+        acc_t += og.Bt.reshape(3, 64)
+        acc_sp += og.Bsp.reshape(3, 64)
+    acc_t /= n
+    acc_sp /= n
+    for g, k in enumerate(ks):
+        tm = exact.transfer_matrix_averages(jx, jy, L_tau, k, k)
+        _check_mean(acc_t[g], tm["Bt"])
+        _check_mean(acc_sp[g], tm["Bsp"])
+    assert og.acc.sum() > 0
+
+
+def test_equal_k_rotate_walkers():
+    """Equal couplings: every exchange is accepted whatever the energies."""
+    N = 4
+    og = chain.OracleGroup(4, 4, 1.0, [0.3] * N, 0, 42, [1] * 64, ladder="k")
+    for _ in range(12):
+        before = og.walker.reshape(N, 64).copy()
+        og.pt_step()
+        after = og.walker.reshape(N, 64)
+        assert np.array_equal(after[N - 1], before[0])
+        assert np.array_equal(after[:N - 1], before[1:])
