@@ -196,6 +196,7 @@ def main():
     physics = summarize(wl, ens)
     ens.close()
     ceiling = philox_ceiling()
+    traffic = measured_traffic(args.workload)
 
     result = {
         "metric": "ps/spin-update (1 GPU) batched vs plain",
@@ -229,7 +230,7 @@ def main():
             "peak": round(PEAK_VALU_TOPS, 4),
             "unit": "T VALU lane-instructions/s",
             "frac": round(achieved / PEAK_VALU_TOPS, 4),
-            "traffic": measured_traffic(args.workload),
+            "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": int(words_per_pass * 12),
             "avg_launch_us": round(pass_s * 1e6, 3),
@@ -240,6 +241,9 @@ def main():
         },
     }
     required_rate = words_per_pass * blocks / pass_s
+    if traffic is not None:
+        result["roofline"]["hbm_GBps_measured"] = round(traffic / pass_s / 1e9, 2)
+        result["roofline"]["hbm_frac_measured"] = round(traffic / pass_s / 8e12, 4)
     result["philox_ceiling"] = dict(ceiling, sweep_required_blocks_per_s=required_rate,
                                     sweep_frac_of_ceiling=round(required_rate / ceiling["blocks_per_s"], 4))
     result["physics"] = physics

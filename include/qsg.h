@@ -80,7 +80,16 @@ typedef struct {
     uint64_t j_seed[64];     /* Philox key of lane j's couplings              */
     uint32_t swap_table_cap; /* max swap-table entries per pair (0 = 4096)    */
     uint32_t ladder_kind;    /* QSG_LADDER_GAMMA (0) or QSG_LADDER_K (1)      */
+    uint32_t tau_boundary;   /* QSG_TAU_PERIODIC (0) or QSG_TAU_ANTIPERIODIC (1) */
+    uint32_t reserved;       /* must be 0                                     */
 } qsg_group_desc;
+
+/* Boundary along imaginary time (Sec. 1 allows both): periodic,
+ * S(tau + L_tau) = S(tau), or antiperiodic, S(tau + L_tau) = -S(tau): the
+ * time bond from slice L_tau-1 to slice 0 then counts with the opposite
+ * sign in Bt and in the Metropolis classes. */
+#define QSG_TAU_PERIODIC 0u
+#define QSG_TAU_ANTIPERIODIC 1u
 
 /* Ladder kinds.  GAMMA: slot g runs the two-coupling form at transverse
  * field Gamma_g (k = beta/L_tau on space bonds, kp_g on time bonds) and PT

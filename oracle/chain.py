@@ -42,10 +42,10 @@ def lib() -> C.CDLL:
                                                C.c_void_p]
         _lib.oracle_init_spins.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint32,
                                            C.c_uint64, C.c_uint32, C.c_void_p]
-        _lib.oracle_site_classes.argtypes = [C.c_int, C.c_int, C.c_void_p,
+        _lib.oracle_site_classes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p,
                                              C.c_void_p, C.c_void_p, C.c_int64,
                                              C.c_int, C.c_void_p, C.c_void_p]
-        _lib.oracle_recompute.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p,
+        _lib.oracle_recompute.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
                                           C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_void_p, C.c_void_p]
     return _lib
@@ -89,14 +89,14 @@ def initial_spins(L, L_tau, N, group_id, seed, slot_base=0) -> np.ndarray:
     return S
 
 
-def site_classes(L, L_tau, Jx, Jy, cfgs: np.ndarray, lane: int = 0):
+def site_classes(L, L_tau, Jx, Jy, cfgs: np.ndarray, lane: int = 0, antiperiodic=False):
     cfgs = np.ascontiguousarray(cfgs, dtype=np.uint64)
     V = L * L * L_tau
     n = cfgs.size // V
     ns = np.zeros(n * V, dtype=np.uint8)
     nt = np.zeros(n * V, dtype=np.uint8)
-    lib().oracle_site_classes(L, L_tau, _p(Jx), _p(Jy), _p(cfgs), n, lane,
-                              _p(ns), _p(nt))
+    lib().oracle_site_classes(L, L_tau, int(bool(antiperiodic)), _p(Jx), _p(Jy), _p(cfgs), n,
+                              lane, _p(ns), _p(nt))
     return ns.reshape(n, V), nt.reshape(n, V)
 
 
@@ -113,7 +113,7 @@ class _State(C.Structure):
         ("swaplog", C.c_void_p), ("log_cap", C.c_uint64),
         ("sum_Bsp", C.c_void_p), ("sum_Bt", C.c_void_p), ("sum_q", C.c_void_p),
         ("sum_q2", C.c_void_p), ("counters", C.c_void_p), ("hist", C.c_void_p),
-        ("slot_base", C.c_uint32), ("exch_all", C.c_uint32),
+        ("slot_base", C.c_uint32), ("tau_anti", C.c_uint32), ("exch_all", C.c_uint32),
     ]
 
 
@@ -126,9 +126,11 @@ class OracleGroup:
 
     def __init__(self, L, L_tau, beta, gammas, group_id, mc_seed, j_seeds,
                  log_cap=4096, thr=None, swap=None, spins=None, slot_base=0,
-                 ladder="gamma"):
+                 ladder="gamma", antiperiodic=False):
         """`gammas` is the ladder: transverse fields (ascending) for
-        ladder="gamma", couplings k_g (descending) for ladder="k"."""
+        ladder="gamma", couplings k_g (descending) for ladder="k".
+        antiperiodic: S(tau + L_tau) = -S(tau) instead of periodic in tau."""
+        self.antiperiodic = bool(antiperiodic)
         if ladder not in ("gamma", "k"):
             raise ValueError("ladder must be 'gamma' or 'k'")
         self.ladder = ladder
@@ -163,7 +165,7 @@ class OracleGroup:
         self.Bsp = np.zeros(N * 64, dtype=np.int32)
         self.Bt = np.zeros(N * 64, dtype=np.int32)
         q = np.zeros(N * 32, dtype=np.int64)
-        lib().oracle_recompute(self.L, self.L_tau, N, _p(self.Jx), _p(self.Jy),
+        lib().oracle_recompute(self.L, self.L_tau, int(self.antiperiodic), N, _p(self.Jx), _p(self.Jy),
                                _p(self.spins), _p(self.Bsp), _p(self.Bt), _p(q))
         self.walker = np.repeat(np.arange(N, dtype=np.uint8), 64)
         self.rt_state = np.zeros(N * 64, dtype=np.uint8)
@@ -188,19 +190,21 @@ class OracleGroup:
             _p(self.rt_tlast), _p(self.rt_count), _p(self.rt_sum), _p(self.acc),
             _p(self.swaplog), self.log_cap, _p(self.sum_Bsp), _p(self.sum_Bt),
             _p(self.sum_q), _p(self.sum_q2), _p(self.counters), _p(self.hist), self.slot_base,
-            1 if ladder == "k" else 0)
+            int(self.antiperiodic), 1 if ladder == "k" else 0)
 
     @classmethod
     def from_workload_group(cls, grp, **kw):
         return cls(grp.L, grp.L_tau, grp.beta, grp.gammas, grp.group_id,
-                   grp.mc_seed, grp.j_seeds, ladder=grp.ladder, **kw)
+                   grp.mc_seed, grp.j_seeds, ladder=grp.ladder,
+                   antiperiodic=grp.antiperiodic, **kw)
 
     @classmethod
     def single_slot(cls, grp, g, **kw):
         """Slot g of a group on its own (valid between PT steps, where the
         slots of a group evolve independently)."""
         return cls(grp.L, grp.L_tau, grp.beta, [grp.gammas[g]], grp.group_id,
-                   grp.mc_seed, grp.j_seeds, slot_base=g, ladder=grp.ladder, **kw)
+                   grp.mc_seed, grp.j_seeds, slot_base=g, ladder=grp.ladder,
+                   antiperiodic=grp.antiperiodic, **kw)
 
     # ------------------------------------------------------------------
     @property
@@ -226,7 +230,7 @@ class OracleGroup:
         Bsp = np.zeros(N * 64, dtype=np.int32)
         Bt = np.zeros(N * 64, dtype=np.int32)
         q = np.zeros(N * 32, dtype=np.int64)
-        lib().oracle_recompute(self.L, self.L_tau, N, _p(self.Jx), _p(self.Jy),
+        lib().oracle_recompute(self.L, self.L_tau, int(self.antiperiodic), N, _p(self.Jx), _p(self.Jy),
                                _p(self.spins), _p(Bsp), _p(Bt), _p(q))
         return Bsp.reshape(N, 64), Bt.reshape(N, 64), q.reshape(N, 32)
 

@@ -32,26 +32,32 @@ def spins_from_index(idx: np.ndarray, V: int) -> np.ndarray:
     return 1 - 2 * b
 
 
-def bond_sums(S: np.ndarray, L: int, L_tau: int, jx: np.ndarray, jy: np.ndarray):
+def bond_sums(S: np.ndarray, L: int, L_tau: int, jx: np.ndarray, jy: np.ndarray,
+              antiperiodic: bool = False):
     """Bsp and Bt of configurations S [n, V] (site s = x + L(y + L tau)).
 
-    jx, jy: +-1 couplings [L*L] of the +x and +y bonds of site (x,y)."""
+    jx, jy: +-1 couplings [L*L] of the +x and +y bonds of site (x,y).
+    antiperiodic: S(tau + L_tau) = -S(tau), i.e. the bond from the last slice
+    to the first counts with the opposite sign."""
     n = S.shape[0]
     S4 = S.reshape(n, L_tau, L, L)  # [n][tau][y][x]
     Jx = jx.reshape(L, L)[None, None]  # [y][x]
     Jy = jy.reshape(L, L)[None, None]
     Bsp = (Jx * S4 * np.roll(S4, -1, axis=3)).sum(axis=(1, 2, 3)) + \
           (Jy * S4 * np.roll(S4, -1, axis=2)).sum(axis=(1, 2, 3))
-    Bt = (S4 * np.roll(S4, -1, axis=1)).sum(axis=(1, 2, 3))
+    up = np.roll(S4, -1, axis=1)
+    if antiperiodic:
+        up[:, L_tau - 1] *= -1
+    Bt = (S4 * up).sum(axis=(1, 2, 3))
     return Bsp.astype(np.int64), Bt.astype(np.int64)
 
 
-def enumerate_states(L: int, L_tau: int, jx, jy):
+def enumerate_states(L: int, L_tau: int, jx, jy, antiperiodic: bool = False):
     V = L * L * L_tau
     assert V <= 20
     idx = np.arange(1 << V, dtype=np.int64)
     S = spins_from_index(idx, V)
-    Bsp, Bt = bond_sums(S, L, L_tau, np.asarray(jx), np.asarray(jy))
+    Bsp, Bt = bond_sums(S, L, L_tau, np.asarray(jx), np.asarray(jy), antiperiodic)
     return idx, Bsp, Bt
 
 
@@ -61,8 +67,8 @@ def boltzmann(Bsp, Bt, k: float, kp: float) -> np.ndarray:
     return w / w.sum()
 
 
-def exact_moments(L, L_tau, jx, jy, k, kp) -> Dict[str, float]:
-    _, Bsp, Bt = enumerate_states(L, L_tau, jx, jy)
+def exact_moments(L, L_tau, jx, jy, k, kp, antiperiodic: bool = False) -> Dict[str, float]:
+    _, Bsp, Bt = enumerate_states(L, L_tau, jx, jy, antiperiodic)
     w = boltzmann(Bsp, Bt, k, kp)
     return {
         "Bsp": float((w * Bsp).sum()),
@@ -73,8 +79,11 @@ def exact_moments(L, L_tau, jx, jy, k, kp) -> Dict[str, float]:
 
 
 def transfer_matrix_averages(jx, jy, L_tau: int, k: float, kp: float,
-                             L: int = 2) -> Dict[str, float]:
-    """<Bsp>, <Bt> for an L x L lattice with L_tau slices, periodic in tau."""
+                             L: int = 2, antiperiodic: bool = False) -> Dict[str, float]:
+    """<Bsp>, <Bt> for an L x L lattice with L_tau slices, periodic in tau
+    (or antiperiodic: the last transfer step carries e^{-kp S.S'}; moving the
+    twist to another bond is a change of variables, so every slice and every
+    time bond, counted with its sign, has the same average)."""
     n = L * L
     idx = np.arange(1 << n)
     s = spins_from_index(idx, n)  # slice states [2^n, n]
@@ -83,8 +92,10 @@ def transfer_matrix_averages(jx, jy, L_tau: int, k: float, kp: float,
     ov = s @ s.T  # sum_x S_x S'_x
     half = np.exp(0.5 * k * b)
     T = half[:, None] * np.exp(kp * ov) * half[None, :]
-    Tn1 = np.linalg.matrix_power(T, L_tau - 1)
-    Tn = Tn1 @ T
+    Tw = half[:, None] * np.exp(-kp * ov) * half[None, :] if antiperiodic else T
+    Tn2 = np.linalg.matrix_power(T, L_tau - 2)
+    Tn1 = Tn2 @ Tw  # every step but the first, the twisted one last
+    Tn = T @ Tn1
     Z = np.trace(Tn)
     Bsp = L_tau * np.trace(np.diag(b.astype(float)) @ Tn) / Z
     Bt = L_tau * np.trace((T * ov) @ Tn1) / Z

@@ -140,7 +140,14 @@ void oracle_init_spins(int L, int Ltau, int N, uint32_t group_id, uint64_t seed,
 /* -------------------------- lattice helpers ------------------------------ */
 typedef struct {
     int L, Ltau;
+    int anti; /* 1: antiperiodic along tau, S(tau + L_tau) = -S(tau) (Sec. 1) */
 } lat_t;
+
+/* Sign of the time bond from slice tau to tau+1: -1 on the bond that wraps
+ * round an antiperiodic prism. */
+static inline int tbond_sign(const lat_t *a, int tau) {
+    return (a->anti && tau == a->Ltau - 1) ? -1 : +1;
+}
 
 static inline size_t site(const lat_t *a, int x, int y, int tau) {
     return (size_t)x + (size_t)a->L * ((size_t)y + (size_t)a->L * (size_t)tau);
@@ -160,6 +167,7 @@ static inline int coup_val(const uint64_t *J, int i, int j) {
 typedef struct {
     uint64_t c, xp, xm, yp, ym, tp, tm; /* centre and its six neighbours   */
     uint64_t jxp, jxm, jyp, jym;        /* couplings of the four space bonds */
+    int stp, stm;                       /* signs of the +tau and -tau bonds  */
 } nbhd_t;
 
 static void load_nbhd(const lat_t *a, const uint64_t *S, const uint64_t *Jx,
@@ -180,12 +188,15 @@ static void load_nbhd(const lat_t *a, const uint64_t *S, const uint64_t *Jx,
     n->jxm = Jx[xm + L * y];
     n->jyp = Jy[x + L * y];
     n->jym = Jy[x + L * ym];
+    n->stp = tbond_sign(a, tau);
+    n->stm = tbond_sign(a, tm);
 }
 
 static inline int pm(uint64_t w, int j) { return bit_of(w, j) ? -1 : +1; }
 
 /* Number of unsatisfied spatial bonds (of 4) and temporal bonds (of 2)
- * around lane j's spin; a bond with J*S*S' < 0 is unsatisfied. */
+ * around lane j's spin; a bond with J*S*S' < 0 is unsatisfied (J = the
+ * bond's sign for time bonds). */
 static void lane_classes(const nbhd_t *n, int j, int *ns, int *nt) {
     int s0 = pm(n->c, j);
     int u = 0;
@@ -194,8 +205,8 @@ static void lane_classes(const nbhd_t *n, int j, int *ns, int *nt) {
     if (pm(n->jyp, j) * s0 * pm(n->yp, j) < 0) u++;
     if (pm(n->jym, j) * s0 * pm(n->ym, j) < 0) u++;
     int v = 0;
-    if (s0 * pm(n->tp, j) < 0) v++;
-    if (s0 * pm(n->tm, j) < 0) v++;
+    if (n->stp * s0 * pm(n->tp, j) < 0) v++;
+    if (n->stm * s0 * pm(n->tm, j) < 0) v++;
     *ns = u;
     *nt = v;
 }
@@ -203,10 +214,10 @@ static void lane_classes(const nbhd_t *n, int j, int *ns, int *nt) {
 /* Exported for the exact tests: (n_s, n_t) of lane 0 at every site for a
  * batch of single-lane configurations.  cfg[b*V + s] holds the spin word of
  * site s in configuration b. */
-void oracle_site_classes(int L, int Ltau, const uint64_t *Jx, const uint64_t *Jy,
+void oracle_site_classes(int L, int Ltau, int anti, const uint64_t *Jx, const uint64_t *Jy,
                          const uint64_t *cfg, int64_t n_cfg, int lane,
                          uint8_t *ns_out, uint8_t *nt_out) {
-    lat_t a = {L, Ltau};
+    lat_t a = {L, Ltau, anti};
     size_t V = (size_t)L * L * Ltau;
     for (int64_t b = 0; b < n_cfg; ++b) {
         const uint64_t *S = cfg + (size_t)b * V;
@@ -227,7 +238,8 @@ void oracle_site_classes(int L, int Ltau, const uint64_t *Jx, const uint64_t *Jy
 /* From-scratch bond sums per lane for one slot (Eq. (3) split into its
  * spatial and temporal parts):
  *   Bsp = sum over sites of Jx S S_{+x} + Jy S S_{+y},
- *   Bt  = sum over sites of S_tau S_{tau+1}. */
+ *   Bt  = sum over sites of S_tau S_{tau+1}, with S_{L_tau} = -S_0 when
+ *         antiperiodic. */
 static void recompute_B(const lat_t *a, const uint64_t *S, const uint64_t *Jx,
                         const uint64_t *Jy, int64_t Bsp[64], int64_t Bt[64]) {
     int L = a->L;
@@ -241,7 +253,8 @@ static void recompute_B(const lat_t *a, const uint64_t *S, const uint64_t *Jx,
                           spin_val(S, site(a, wrap(x + 1, L), y, tau), j);
                     bs += coup_val(Jy, x + L * y, j) * s0 *
                           spin_val(S, site(a, x, wrap(y + 1, L), tau), j);
-                    bt += s0 * spin_val(S, site(a, x, y, wrap(tau + 1, a->Ltau)), j);
+                    bt += tbond_sign(a, tau) * s0 *
+                          spin_val(S, site(a, x, y, wrap(tau + 1, a->Ltau)), j);
                 }
         Bsp[j] = bs;
         Bt[j] = bt;
@@ -260,10 +273,10 @@ static void overlap_pairs(const lat_t *a, const uint64_t *S, int64_t q[32]) {
     }
 }
 
-void oracle_recompute(int L, int Ltau, int N, const uint64_t *Jx,
+void oracle_recompute(int L, int Ltau, int anti, int N, const uint64_t *Jx,
                       const uint64_t *Jy, const uint64_t *spins, int32_t *Bsp,
                       int32_t *Bt, int64_t *q) {
-    lat_t a = {L, Ltau};
+    lat_t a = {L, Ltau, anti};
     size_t V = (size_t)L * L * Ltau;
     for (int g = 0; g < N; ++g) {
         int64_t bs[64], bt[64], qq[32];
@@ -308,6 +321,7 @@ typedef struct {
                                 full ladder (random-number counters only); lets a
                                 test follow a few slots of a large group between
                                 PT steps, where slots evolve independently     */
+    uint32_t tau_anti;       /* 1: antiperiodic boundary along tau        */
     uint32_t exch_all;       /* 0: the slots differ in the time coupling only
                                 (transverse-field ladder), the exchange uses Bt;
                                 1: one coupling k_g on every bond (k ladder), the
@@ -315,7 +329,7 @@ typedef struct {
 } oracle_state;
 
 static void pt_step(oracle_state *st, int *failed) {
-    lat_t a = {st->L, st->Ltau};
+    lat_t a = {st->L, st->Ltau, (int)st->tau_anti};
     const int N = st->N;
     const size_t V = (size_t)st->L * st->L * st->Ltau;
     const uint32_t p = (uint32_t)st->counters[1];
@@ -422,7 +436,7 @@ static void pt_step(oracle_state *st, int *failed) {
 
 /* One colour pass over one slot. */
 static void colour_pass(oracle_state *st, int g, int colour, uint32_t t) {
-    lat_t a = {st->L, st->Ltau};
+    lat_t a = {st->L, st->Ltau, (int)st->tau_anti};
     const size_t V = (size_t)st->L * st->L * st->Ltau;
     uint64_t *S = st->spins + (size_t)g * V;
     const uint32_t *thr = st->thr + (size_t)g * 15;

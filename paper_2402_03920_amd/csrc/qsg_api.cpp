@@ -73,6 +73,10 @@ bool valid_desc(const qsg_group_desc& d, std::string* why) {
         std::snprintf(buf, sizeof buf, "L*L*L_tau too large");
     } else if (d.ladder_kind != QSG_LADDER_GAMMA && d.ladder_kind != QSG_LADDER_K) {
         std::snprintf(buf, sizeof buf, "ladder_kind=%u unknown", d.ladder_kind);
+    } else if (d.tau_boundary != QSG_TAU_PERIODIC && d.tau_boundary != QSG_TAU_ANTIPERIODIC) {
+        std::snprintf(buf, sizeof buf, "tau_boundary=%u unknown", d.tau_boundary);
+    } else if (d.reserved != 0) {
+        std::snprintf(buf, sizeof buf, "reserved field must be 0");
     } else if (swap_cap_of(d) > (1u << 24)) {
         std::snprintf(buf, sizeof buf, "swap_table_cap too large");
     } else {
@@ -457,6 +461,7 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         g.log_cap = cfg->swaplog_cap;
         g.q_split = cfg->sweep_split ? (cfg->sweep_split > 16 ? 16 : cfg->sweep_split) : 4;
         g.exch_all = d.ladder_kind == QSG_LADDER_K ? 1u : 0u;
+        g.anti = d.tau_boundary == QSG_TAU_ANTIPERIODIC ? 1u : 0u;
         g.spins = at<uint64_t>(c, gl.spins);
         g.Jx = at<uint64_t>(c, gl.Jx);
         g.Jy = at<uint64_t>(c, gl.Jy);

@@ -64,6 +64,7 @@ struct GroupDev {
     uint32_t log_cap;     // rows of the swap log
     uint32_t q_split;     // colour-pass schedule: Philox blocks before packing
     uint32_t exch_all;    // PT energy: 0 time bonds (Gamma ladder), 1 all bonds (k ladder)
+    uint32_t anti;        // 1: antiperiodic along tau (the wrapping time bond flips sign)
     Divisor div_half_plane, div_half_row, div_plane, div_row;
     Divisor div_blocks;   // colour-pass blocks per slot
     uint64_t* spins;          // [N][Ltau][L][L]

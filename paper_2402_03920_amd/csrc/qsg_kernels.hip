@@ -195,8 +195,8 @@ __device__ __forceinline__ WordState load_site(const GroupDev& G, const uint64_t
     const uint64_t nxm = load64<kGlobal>(S, plane + row + xm);
     const uint64_t nyp = load64<kGlobal>(S, plane + yp * L + x);
     const uint64_t nym = load64<kGlobal>(S, plane + ym * L + x);
-    const uint64_t ntp = load64<kGlobal>(S, tp * P + row + x);
-    const uint64_t ntm = load64<kGlobal>(S, tm * P + row + x);
+    const uint64_t ntp_raw = load64<kGlobal>(S, tp * P + row + x);
+    const uint64_t ntm_raw = load64<kGlobal>(S, tm * P + row + x);
     const uint64_t jxp = load64<true>(G.Jx, row + x);
     const uint64_t jxm = load64<true>(G.Jx, row + xm);  // the -x bond is the +x bond of x-1
     const uint64_t jyp = load64<true>(G.Jy, row + x);
@@ -211,7 +211,15 @@ __device__ __forceinline__ WordState load_site(const GroupDev& G, const uint64_t
     st.s0 = sum ^ u4;
     st.s1 = bop3<kXorAnd>(carry, sum, u4);
     st.s2 = bop3<kAnd3>(carry, sum, u4);
-    // unsatisfied time bonds n_t as one-hot planes
+    // unsatisfied time bonds n_t as one-hot planes; on an antiperiodic prism
+    // the bond that wraps round tau counts with the opposite sign, which is
+    // the neighbour's word inverted
+    uint64_t ntp = ntp_raw, ntm = ntm_raw;
+    if (G.anti) {
+        asm volatile("");  // a block-uniform branch: periodic groups skip this
+        if (tau + 1 == G.Ltau) ntp = ~ntp;
+        if (tau == 0) ntm = ~ntm;
+    }
     st.nt0 = bop3<kEqEq>(w, ntp, ntm);
     st.nt1 = ntp ^ ntm;
     st.nt2 = bop3<kNeNe>(w, ntp, ntm);
@@ -551,6 +559,13 @@ k_chunk_fused(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ 
 // Bit-sliced per-lane counter: value = ones + 2 twos + 4 fours + 8 * (hi as
 // a binary number).  Planes are added eight at a time with carry-save adders
 // (Harley-Seal), so each added plane costs about two bitop3 per 32 lanes.
+// Binary planes a LaneCounter needs above ones/twos/fours to hold `max`.
+constexpr int counter_planes(int max) {
+    int nh = 0;
+    while ((8 << nh) - 1 < max) ++nh;
+    return nh;
+}
+
 template <int NH>
 struct LaneCounter {
     uint64_t ones = 0, twos = 0, fours = 0;
@@ -602,9 +617,10 @@ __device__ __forceinline__ void energy_block(const GroupDev& G, uint32_t g, uint
     static_assert(kEnergyWords % 8 == 0, "words come in chunks of eight");
     const uint32_t L = G.L, P = L * L, V = G.V;
     const uint64_t* __restrict__ S = G.spins + (size_t)g * V;
-    // per thread at most 2*kEnergyWords = 64 unsatisfied space bonds per lane
-    LaneCounter<4> Csp;
-    LaneCounter<3> Ct, Cq;
+    // per thread and lane at most 2*kEnergyWords unsatisfied space bonds and
+    // kEnergyWords time bonds or differing pairs
+    LaneCounter<counter_planes(2 * kEnergyWords)> Csp;
+    LaneCounter<counter_planes(kEnergyWords)> Ct, Cq;
     const uint32_t first = blk * (kEnergyBlock * kEnergyWords) + threadIdx.x;
 #pragma unroll 1
     for (int k0 = 0; k0 < kEnergyWords; k0 += 8) {
@@ -625,6 +641,7 @@ __device__ __forceinline__ void energy_block(const GroupDev& G, uint32_t g, uint
                 xs[k] = w ^ S[tau * P + y * L + xp] ^ G.Jx[rem];  // +x bond unsatisfied
                 ys[k] = w ^ S[tau * P + yp * L + x] ^ G.Jy[rem];  // +y bond unsatisfied
                 ts[k] = w ^ S[tp * P + rem];                        // +tau bond unsatisfied
+                if (G.anti && tp == 0) ts[k] = ~ts[k];              // antiperiodic wrap bond
                 qs[k] = (w ^ (w >> 1)) & 0x5555555555555555ull;     // pair (2p, 2p+1) differs
             }
         }

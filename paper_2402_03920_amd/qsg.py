@@ -50,7 +50,8 @@ class qsg_group_desc(C.Structure):
     _fields_ = [("L", C.c_uint32), ("L_tau", C.c_uint32), ("beta", C.c_double),
                 ("n_gamma", C.c_uint32), ("group_id", C.c_uint32),
                 ("mc_seed", C.c_uint64), ("j_seed", C.c_uint64 * 64),
-                ("swap_table_cap", C.c_uint32), ("ladder_kind", C.c_uint32)]
+                ("swap_table_cap", C.c_uint32), ("ladder_kind", C.c_uint32),
+                ("tau_boundary", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class qsg_run_config(C.Structure):
@@ -176,7 +177,7 @@ LADDER_KINDS = {"gamma": 0, "k": 1}
 
 
 def make_desc(L, L_tau, beta, n_gamma, group_id, mc_seed, j_seeds,
-              swap_table_cap=0, ladder="gamma") -> qsg_group_desc:
+              swap_table_cap=0, ladder="gamma", antiperiodic=False) -> qsg_group_desc:
     d = qsg_group_desc()
     d.L, d.L_tau, d.beta = int(L), int(L_tau), float(beta)
     d.n_gamma, d.group_id, d.mc_seed = int(n_gamma), int(group_id), int(mc_seed)
@@ -187,6 +188,8 @@ def make_desc(L, L_tau, beta, n_gamma, group_id, mc_seed, j_seeds,
         d.j_seed[j] = int(s)
     d.swap_table_cap = int(swap_table_cap)
     d.ladder_kind = LADDER_KINDS[ladder]
+    d.tau_boundary = 1 if antiperiodic else 0
+    d.reserved = 0
     return d
 
 
@@ -208,7 +211,8 @@ class Ensemble:
         for i, g in enumerate(self.groups):
             self.descs[i] = make_desc(g.L, g.L_tau, g.beta, len(g.gammas), g.group_id,
                                       g.mc_seed, g.j_seeds, swap_table_cap,
-                                      getattr(g, "ladder", "gamma"))
+                                      getattr(g, "ladder", "gamma"),
+                                      getattr(g, "antiperiodic", False))
         self.cfg = qsg_run_config(int(pt_every), int(swaplog_cap), int(sweep_split), 0)
         nbytes = L_.qsg_workspace_bytes(self.descs, self.n, C.byref(self.cfg))
         if nbytes == 0:

@@ -58,6 +58,7 @@ class Group:
     mc_seed: int
     j_seeds: List[int]
     ladder: str = "gamma"
+    antiperiodic: bool = False  # S(tau + L_tau) = -S(tau) (else periodic in tau)
 
     @property
     def n_gamma(self) -> int:
@@ -187,10 +188,11 @@ def tiny_k_group(L=4, L_tau=8, n_k=3, kmax=0.5, kmin=0.2, group_id=0, mc_seed=MC
 
 
 def tiny_group(L=4, L_tau=8, beta=1.0, n_gamma=3, gmin=0.5, gmax=2.0,
-               group_id=0, mc_seed=MC_SEED, j_seed=1, per_lane=False) -> Group:
+               group_id=0, mc_seed=MC_SEED, j_seed=1, per_lane=False,
+               antiperiodic=False) -> Group:
     lad = geometric_ladder(gmin, gmax, n_gamma)
     seeds = [j_seed + j for j in range(64)] if per_lane else _replicas(j_seed)
-    return Group(L, L_tau, beta, lad, group_id, mc_seed, seeds)
+    return Group(L, L_tau, beta, lad, group_id, mc_seed, seeds, antiperiodic=antiperiodic)
 
 
 ALL = {

@@ -144,3 +144,13 @@ def test_binary128_k_tables_equal_oracle_mpmath(case):
     for g, t in enumerate(otabs):
         assert np.array_equal(sw[g, :len(t)], t)
         assert np.all(sw[g, len(t):] == 0)
+
+
+def test_tau_boundary_is_validated():
+    assert _ws_bytes(_desc(antiperiodic=True)) > 0
+    d = _desc()
+    d.tau_boundary = 2
+    assert _ws_bytes(d) == 0
+    d = _desc()
+    d.reserved = 1
+    assert _ws_bytes(d) == 0

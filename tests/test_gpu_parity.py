@@ -7,6 +7,7 @@ while spanning several thread blocks and ragged tails; the full-size
 production shape is checked on sampled slots.
 """
 import sys
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -135,6 +136,32 @@ def test_k_ladder_groups_bit_exact(mode):
                 og.run(n, 5)
             compare_state(ens, ogs)
         assert all(int(og.acc.sum()) > 0 for og in ogs[:3])
+
+
+@pytest.mark.parametrize("mode", ["plain", "graph", "fused_graph"])
+def test_antiperiodic_groups_bit_exact(mode):
+    """Antiperiodic prisms (the wrapping time bond counts with the opposite
+    sign) for both ladder kinds, next to a periodic group."""
+    groups = [
+        W.tiny_group(L=4, L_tau=8, beta=1.5, n_gamma=4, gmin=0.5, gmax=2.5, group_id=20,
+                     antiperiodic=True),
+        W.tiny_group(L=6, L_tau=2, beta=1.0, n_gamma=3, group_id=21, per_lane=True, j_seed=40,
+                     antiperiodic=True),
+        W.tiny_group(L=12, L_tau=10, beta=2.0, n_gamma=5, gmin=0.8, gmax=1.6, group_id=22,
+                     j_seed=41, antiperiodic=True),
+        replace(W.tiny_k_group(L=8, L_tau=6, n_k=4, kmax=0.5, kmin=0.3, group_id=23),
+                antiperiodic=True),
+        small_groups()[0],
+    ]
+    say(f"[parity] antiperiodic groups, mode={mode}")
+    ogs = oracle_groups(groups, 32)
+    with qsg.Ensemble(groups, pt_every=5, swaplog_cap=32) as ens:
+        ens.init_spins()
+        for n in (7, 13, 20):
+            ens.sweep(n, MODES[mode])
+            for og in ogs:
+                og.run(n, 5)
+            compare_state(ens, ogs)
 
 
 def test_k_ladder_workload_truncated_bit_exact():

@@ -469,3 +469,58 @@ def test_equal_k_rotate_walkers():
         after = og.walker.reshape(N, 64)
         assert np.array_equal(after[N - 1], before[0])
         assert np.array_equal(after[:N - 1], before[1:])
+
+
+# ------------------------------------------------------------------------
+# Antiperiodic boundary along tau (Sec. 1: S(tau + L_tau) = -S(tau)).
+
+def test_antiperiodic_enumeration_matches_transfer_matrix():
+    _, _, jx, jy = _lane0_couplings(2, 5)
+    for L_tau in (2, 4):
+        e = exact.exact_moments(2, L_tau, jx, jy, 0.25, 0.7, antiperiodic=True)
+        tm = exact.transfer_matrix_averages(jx, jy, L_tau, 0.25, 0.7, antiperiodic=True)
+        assert abs(e["Bsp"] - tm["Bsp"]) < 1e-10
+        assert abs(e["Bt"] - tm["Bt"]) < 1e-10
+    # the twist matters: the periodic averages differ
+    per = exact.exact_moments(2, 4, jx, jy, 0.25, 0.7)
+    assert abs(per["Bt"] - e["Bt"]) > 1e-3
+
+
+@pytest.mark.parametrize("beta,G", [(1.0, 1.0), (2.0, 3.0)])
+def test_antiperiodic_colour_pass_keeps_boltzmann_stationary(beta, G):
+    """As for the periodic prism: the exact colour-pass operators built from
+    the oracle's own antiperiodic classes keep the antiperiodic Boltzmann
+    weight stationary; the periodic classes do not."""
+    L, L_tau = 2, 4
+    Jx, Jy, jx, jy = _lane0_couplings(L, 3)
+    k = beta / L_tau
+    kp = -0.5 * math.log(math.tanh(beta * G / L_tau))
+    idx, Bsp, Bt = exact.enumerate_states(L, L_tau, jx, jy, antiperiodic=True)
+    pi = exact.boltzmann(Bsp, Bt, k, kp)
+    V = L * L * L_tau
+    cfg = ((idx[:, None] >> np.arange(V)[None, :]) & 1).astype(np.uint64)
+    thr = tables.metropolis_thresholds(beta, L_tau, [G])[0].astype(np.float64)
+    ns, nt = chain.site_classes(L, L_tau, Jx, Jy, cfg.reshape(-1), antiperiodic=True)
+    p = (thr[ns, nt] + 1.0) / U32
+    for colour in (0, 1):
+        out = exact.half_sweep_apply(pi, p, exact.colour_sites(L, L_tau, colour))
+        assert float(np.max(np.abs(out - pi))) < 1e-8
+    ns0, nt0 = chain.site_classes(L, L_tau, Jx, Jy, cfg.reshape(-1))
+    p0 = (thr[ns0, nt0] + 1.0) / U32
+    dev = np.max(np.abs(exact.half_sweep_apply(pi, p0, exact.colour_sites(L, L_tau, 0)) - pi))
+    assert dev > 1e-6  # far above the 1e-8 stationarity tolerance (weak kp at G = 3)
+
+
+def test_antiperiodic_chain_matches_transfer_matrix_Ltau32():
+    L, L_tau, beta, G = 2, 32, 4.0, 2.0
+    _, _, jx, jy = _lane0_couplings(L, 11)
+    og = chain.OracleGroup(L, L_tau, beta, [G], 0, 42, [11] * 64, antiperiodic=True)
+    msp, mt = _lane_means(og, 2000)
+    k = beta / L_tau
+    kp = -0.5 * math.log(math.tanh(beta * G / L_tau))
+    tm = exact.transfer_matrix_averages(jx, jy, L_tau, k, kp, antiperiodic=True)
+    _check_mean(msp[0], tm["Bsp"])
+    _check_mean(mt[0], tm["Bt"])
+    # an odd number of unsatisfied time bonds in every tau column
+    V = L * L * L_tau
+    assert np.all(((V - og.Bt) // 2) % 2 == (L * L) % 2)
