@@ -27,6 +27,10 @@ sys.path.insert(0, ROOT)
 # 32-bit integer instructions used here, v_mad_u64_u32 included, all issue at
 # that rate)
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# HBM bytes a colour pass must move per updated word: every word of the slot
+# is read once (the updated colour and its neighbours, 2 x 8 B per updated
+# word) and the updated word is written (8 B)
+BYTES_PER_UPDATED_WORD = 24
 # fewest gfx950 VALU instructions for one Philox4x32-10 block per lane:
 # 10 rounds x (2 v_mad_u64_u32 + 2 three-input xors)
 INSTR_PER_PHILOX_BLOCK = 40
@@ -232,12 +236,12 @@ def main():
             "frac": round(achieved / PEAK_VALU_TOPS, 4),
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "algorithmic_bytes_per_launch": int(words_per_pass * 12),
+            "algorithmic_bytes_per_launch": int(words_per_pass * BYTES_PER_UPDATED_WORD),
             "avg_launch_us": round(pass_s * 1e6, 3),
             "algorithmic_ops_per_launch": ops_per_pass,
             "model": f"required Philox work only: {blocks:.4f} blocks/word x "
                      f"{INSTR_PER_PHILOX_BLOCK} instr x {int(words_per_pass)} words/launch",
-            "hbm_GBps_algorithmic": round(words_per_pass * 12 / pass_s / 1e9, 2),
+            "hbm_GBps_algorithmic": round(words_per_pass * BYTES_PER_UPDATED_WORD / pass_s / 1e9, 2),
         },
     }
     required_rate = words_per_pass * blocks / pass_s
@@ -336,22 +340,23 @@ def cpu_baseline(wl, n_sweeps):
     og.run(n_sweeps, 0, threads=threads)
     dt = time.perf_counter() - t0
     upd = n_sweeps * g.spin_updates_per_sweep
-    # the same oracle on one core, over a fresh copy of the sample: a sixteenth
-    # of the sweeps (at least one)
-    n1 = max(1, n_sweeps // 16)
-    og1 = chain.OracleGroup.from_workload_group(g, log_cap=8)
+    # the same oracle on one core: the first slot of the sample on its own
+    # (slots evolve independently between PT steps), about 5-15 s of work
+    per_slot = g.spin_updates_per_sweep // len(g.gammas)
+    n1 = max(1, int(round(2.5e8 / per_slot)))
+    og1 = chain.OracleGroup.single_slot(g, 0, log_cap=8)
     t1 = time.perf_counter()
     og1.run(n1, 0, threads=1)
     dt1 = time.perf_counter() - t1
-    upd1 = n1 * g.spin_updates_per_sweep
+    upd1 = n1 * per_slot
     return {"value": round(dt / upd * 1e12, 2), "unit": "ps/spin-update", "cores": threads,
             "kind": "oracle",
             "sample": f"1 of {len(wl.groups)} groups (L={g.L}, L_tau={g.L_tau}, "
                       f"{len(g.gammas)} Gammas), {n_sweeps} sweeps, no PT; {upd:.3e} "
                       f"spin-updates in {dt:.1f} s",
             "single_core_ps_per_spin_update": round(dt1 / upd1 * 1e12, 2),
-            "single_core_sample": f"{n1} sweeps of the same sample, {upd1:.3e} spin-updates "
-                                  f"in {dt1:.1f} s",
+            "single_core_sample": f"slot 0 of the same sample, {n1} sweeps, {upd1:.3e} "
+                                  f"spin-updates in {dt1:.1f} s",
             "host_cpu": host_cpu(), "host_cpus_visible": cores}
 
 

@@ -3,13 +3,14 @@
  * tempering over the Trotter-Suzuki (2+1)-D lattice of the 2D +-J quantum
  * Ising spin glass (paper: "The QISG suite", Sec. 1 Eqs. (1)-(3), Sec. 2.1).
  *
- * Model.  Spins S(x,y,tau) = +-1 on an L x L x L_tau prism, periodic in all
- * three directions (Sec. 1).  Space bonds (x,y)-(x+1,y) and (x,y)-(x,y+1)
- * carry J = +-1 and coupling k = beta/L_tau; time bonds (x,y,tau)-(x,y,tau+1)
- * carry kp_g = -1/2 ln tanh(beta Gamma_g / L_tau) (two-coupling form; the
- * paper's equal-coupling form, Sec. 1, is kp = k).  A configuration at slot
- * g has weight exp(k Bsp + kp_g Bt), with Bsp the sum of J S S' over space
- * bonds and Bt the sum of S S' over time bonds (Eq. (3) split in two).
+ * Model.  Spins S(x,y,tau) = +-1 on an L x L x L_tau prism, periodic in
+ * space and periodic or antiperiodic in tau (Sec. 1; see tau_boundary).
+ * Space bonds (x,y)-(x+1,y) and (x,y)-(x,y+1) carry J = +-1 and coupling
+ * k = beta/L_tau; time bonds (x,y,tau)-(x,y,tau+1) carry
+ * kp_g = -1/2 ln tanh(beta Gamma_g / L_tau) (two-coupling form; the paper's
+ * equal-coupling form, Sec. 1, is kp = k: see ladder_kind).  A configuration
+ * at slot g has weight exp(k Bsp + kp_g Bt), with Bsp the sum of J S S' over
+ * space bonds and Bt the sum of S S' over time bonds (Eq. (3) split in two).
  *
  * Packing.  A *group* is 64 independent bit-lanes that share L, L_tau,
  * beta, the Gamma ladder and the Monte Carlo key.  Lane j of every word is
