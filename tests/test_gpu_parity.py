@@ -164,6 +164,22 @@ def test_antiperiodic_groups_bit_exact(mode):
             compare_state(ens, ogs)
 
 
+def test_maximum_slots_bit_exact():
+    """QSG_MAX_GAMMA = 64 slots (63 exchange pairs per PT step) on a small
+    prism, PT every second sweep."""
+    groups = [W.tiny_group(L=4, L_tau=4, beta=1.0, n_gamma=64, gmin=0.3, gmax=3.0,
+                           group_id=30),
+              W.tiny_k_group(L=4, L_tau=6, n_k=64, kmax=0.9, kmin=0.1, group_id=31)]
+    ogs = oracle_groups(groups, 64)
+    with qsg.Ensemble(groups, pt_every=2, swaplog_cap=64) as ens:
+        ens.init_spins()
+        ens.sweep(30, qsg.QSG_BATCHED | qsg.QSG_GRAPH)
+        for og in ogs:
+            og.run(30, 2)
+        compare_state(ens, ogs)
+        assert all(int(og.acc.sum()) > 0 for og in ogs)
+
+
 def test_k_ladder_workload_truncated_bit_exact():
     """Two samples of the k-ladder workload (L=16, L_tau=128, 32 k in
     [0.25, 0.33]), 20 sweeps with PT every 10."""
