@@ -17,6 +17,7 @@
 
 #include "../../include/qsg.h"
 #include "qsg_internal.h"
+#include "qsg_overlaps.h"
 #include "qsg_mlp.h"
 
 extern "C" int qsg_tables_build_host(double beta, uint32_t L_tau, uint32_t N, const double* gamma,
@@ -916,6 +917,30 @@ qsg_status qsg_philox(const uint32_t* d_in, uint32_t* d_out, uint32_t n, void* h
     if (!d_in || !d_out) return fail(nullptr, QSG_E_INVALID, "null buffer");
     hipError_t e = qsg::launch_philox(d_in, d_out, n, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return fail(nullptr, QSG_E_DEVICE, "philox launch: %s", hipGetErrorString(e));
+    return QSG_OK;
+}
+
+qsg_status qsg_tau_overlaps(qsg_ctx* c, uint32_t group, uint32_t slot, const uint32_t* taus,
+                            uint32_t n_taus, int64_t* d_out, size_t out_words) {
+    if (qsg_status st = check_ctx(c)) return st;
+    if (group >= c->gd.size()) return fail(c, QSG_E_INVALID, "group %u out of range", group);
+    const GroupDev& g = c->gd[group];
+    if (slot >= g.N) return fail(c, QSG_E_INVALID, "slot %u out of range", slot);
+    if (g.L > qsg::kOvMaxL)
+        return fail(c, QSG_E_UNSUPPORTED, "tau overlaps need L <= %u", qsg::kOvMaxL);
+    if (!taus || n_taus == 0 || n_taus > qsg::kOvMaxTaus)
+        return fail(c, QSG_E_INVALID, "need 1..%u tau values", qsg::kOvMaxTaus);
+    qsg::TauList tl{};
+    tl.n = n_taus;
+    for (uint32_t i = 0; i < n_taus; ++i) {
+        if (taus[i] >= g.Ltau) return fail(c, QSG_E_INVALID, "tau %u >= L_tau", taus[i]);
+        tl.t[i] = taus[i];
+    }
+    const size_t need = (size_t)n_taus * (2 * 64 + 2 * g.L);
+    if (!d_out) return fail(c, QSG_E_INVALID, "output is null");
+    if (out_words < need) return fail(c, QSG_E_BUFFER, "output needs %zu int64", need);
+    QSG_HIP(c, qsg::launch_tau_overlaps(g.spins + (size_t)slot * g.V, g.L, g.Ltau, tl, d_out,
+                                        c->stream));
     return QSG_OK;
 }
 

@@ -101,6 +101,8 @@ _SIGS = {
     "qsg_destroy": (None, [C.c_void_p]),
     "qsg_philox": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
     "qsg_philox_probe": (C.c_int32, [C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "qsg_tau_overlaps": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint32,
+                                     C.c_void_p, C.c_size_t]),
     "qsg_mlp_param_count": (C.c_uint32, []),
     "qsg_mlp_workspace_floats": (C.c_size_t, [C.c_uint32]),
     "qsg_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
@@ -263,6 +265,25 @@ class Ensemble:
             raise ValueError("ladder length differs from n_gamma")
         _check(lib().qsg_set_k_ladder(self.ctx, i, _ptr(k)), self.ctx)
 
+    def tau_overlaps(self, group: int, slot: int, taus) -> dict:
+        """Contributions of the configuration now in (group, slot) to the
+        Euclidean-time overlaps (qsg_tau_overlaps): int64 arrays q2, q4
+        [64][n_taus] and A, B [n_taus][L]; sum them over configurations and
+        pass the sums to tau_observables."""
+        torch = self._torch
+        t = np.ascontiguousarray(np.asarray(taus, dtype=np.uint32))
+        L = int(self.descs[group].L)
+        n = t.size
+        words = n * (128 + 2 * L)
+        out = torch.zeros(words, dtype=torch.int64, device=self.workspace.device)
+        _check(lib().qsg_tau_overlaps(self.ctx, group, slot, _ptr(t), n,
+                                      C.c_void_p(out.data_ptr()), words), self.ctx)
+        self.sync()
+        a = out.cpu().numpy()
+        return {"q2": a[:64 * n].reshape(64, n), "q4": a[64 * n:128 * n].reshape(64, n),
+                "A": a[128 * n:128 * n + n * L].reshape(n, L),
+                "B": a[128 * n + n * L:].reshape(n, L)}
+
     def init_spins(self):
         _check(lib().qsg_init_spins(self.ctx), self.ctx)
 
@@ -403,6 +424,17 @@ def philox_device(inputs: np.ndarray) -> np.ndarray:
                             a.shape[0], C.c_void_p(s.cuda_stream)))
     torch.cuda.synchronize()
     return d_out.cpu().numpy().view(np.uint32)
+
+
+def tau_observables(acc: dict, L: int, L_tau: int, n_configs: int) -> dict:
+    """Q2(tau), Q4(tau), F(tau) (App. E normalisation: averages over tau1,
+    configurations and the 64 replicas) from summed tau_overlaps output."""
+    import math
+    norm = float(L_tau) * n_configs
+    w = np.array([math.cos(2 * math.pi * d / L) for d in range(L)])
+    return {"Q2": acc["q2"].astype(np.float64).mean(axis=0) / norm,
+            "Q4": acc["q4"].astype(np.float64).mean(axis=0) / norm,
+            "F": ((acc["A"] + acc["B"]).astype(np.float64) @ w) / (2.0 * norm * 64)}
 
 
 def philox_probe(out, n_threads: int, blocks: int, key: int, stream) -> None:

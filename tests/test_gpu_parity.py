@@ -387,3 +387,39 @@ def test_state_does_not_depend_on_reused_memory():
             ens.sweep(10, qsg.QSG_BATCHED)
             states.append(ens.get_state())
     assert np.array_equal(states[0], states[1])
+
+
+def test_tau_overlaps_match_oracle():
+    """Euclidean-time overlaps (App. E) of live configurations, integer sums
+    compared exactly with the oracle on the same spins: ragged L_tau (blocks
+    of four slices), L = 32 (the largest supported), an antiperiodic prism,
+    repeated calls accumulating."""
+    from oracle import overlaps
+    groups = [W.tiny_group(L=6, L_tau=10, beta=2.0, n_gamma=3, group_id=40, per_lane=True,
+                           j_seed=7),
+              W.tiny_group(L=32, L_tau=4, beta=1.0, n_gamma=2, group_id=41),
+              W.tiny_group(L=4, L_tau=6, beta=1.5, n_gamma=2, group_id=42, antiperiodic=True)]
+    with qsg.Ensemble(groups, pt_every=5, swaplog_cap=8) as ens:
+        ens.init_spins()
+        ens.sweep(7, qsg.QSG_BATCHED)
+        for gi, g in enumerate(groups):
+            taus = sorted(set([0, 1, g.L_tau // 2, g.L_tau - 1]))
+            spins = ens.get_spins(gi)
+            V = g.L * g.L * g.L_tau
+            for slot in range(len(g.gammas)):
+                got = ens.tau_overlaps(gi, slot, taus)
+                want = overlaps.contributions(spins[slot * V:(slot + 1) * V], g.L, g.L_tau, taus)
+                for key in ("q2", "q4", "A", "B"):
+                    assert np.array_equal(got[key], want[key]), (gi, slot, key)
+        # observables from two configurations
+        g = groups[0]
+        taus = list(range(g.L_tau))
+        acc = ens.tau_overlaps(0, 1, taus)
+        ens.sweep(3, qsg.QSG_BATCHED)
+        more = ens.tau_overlaps(0, 1, taus)
+        acc = {k: acc[k] + more[k] for k in acc}
+        obs = qsg.tau_observables(acc, g.L, g.L_tau, 2)
+        assert abs(obs["Q2"][0] - g.L ** 4) < 1e-9 and abs(obs["F"][0]) < 1e-6
+        assert np.allclose(obs["Q2"][1:], obs["Q2"][1:][::-1])
+        with pytest.raises(qsg.QSGError):
+            ens.tau_overlaps(0, 0, [g.L_tau])

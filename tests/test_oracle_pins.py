@@ -524,3 +524,69 @@ def test_antiperiodic_chain_matches_transfer_matrix_Ltau32():
     # an odd number of unsatisfied time bonds in every tau column
     V = L * L * L_tau
     assert np.all(((V - og.Bt) // 2) % 2 == (L * L) % 2)
+
+
+# ------------------------------------------------------------------------
+# Euclidean-time overlaps (App. E): the oracle against definitions written
+# out site by site, closed forms and symmetries.
+
+def _random_words(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, 2 ** 63, size=n, dtype=np.int64).astype(np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, size=n, dtype=np.int64).astype(np.uint64)
+
+
+def test_tau_overlaps_match_site_by_site_definition():
+    from oracle import overlaps
+    L, L_tau = 3, 4
+    words = _random_words(L * L * L_tau, 71)
+    taus = [0, 1, 3]
+    got = overlaps.contributions(words, L, L_tau, taus)
+    for a in (0, 5, 63):
+        spin = lambda x, y, t: -1 if (int(words[(t % L_tau) * L * L + y * L + x]) >> a) & 1 else 1
+        for i, tau in enumerate(taus):
+            q2 = q4 = 0
+            for t1 in range(L_tau):
+                Qt = sum(spin(x, y, t1) * spin(x, y, t1 + tau) for x in range(L) for y in range(L))
+                q2 += Qt ** 2
+                q4 += Qt ** 4
+            assert got["q2"][a, i] == q2 and got["q4"][a, i] == q4
+    # F through the integer correlations equals the complex sums
+    i, tau = 1, 1
+    direct = 0.0
+    for a in range(64):
+        for t1 in range(L_tau):
+            for axis in (0, 1):
+                z = 0j
+                for x in range(L):
+                    for y in range(L):
+                        b1 = (int(words[t1 * L * L + y * L + x]) >> a) & 1
+                        b2 = (int(words[((t1 + tau) % L_tau) * L * L + y * L + x]) >> a) & 1
+                        q = 1 - 2 * (b1 ^ b2)
+                        z += q * complex(math.cos(2 * math.pi * (x if axis == 0 else y) / L),
+                                         math.sin(2 * math.pi * (x if axis == 0 else y) / L))
+                direct += abs(z) ** 2
+    w = np.array([math.cos(2 * math.pi * d / L) for d in range(L)])
+    assert abs(float((got["A"][i] + got["B"][i]) @ w) - direct) < 1e-6 * direct
+
+
+def test_tau_overlaps_closed_forms_and_symmetry():
+    from oracle import overlaps
+    L, L_tau = 4, 8
+    words = _random_words(L * L * L_tau, 5)
+    taus = list(range(L_tau))
+    c = overlaps.contributions(words, L, L_tau, taus)
+    # tau = 0: every q is 1
+    assert np.all(c["q2"][:, 0] == L_tau * L ** 4)
+    assert np.all(c["q4"][:, 0] == L_tau * L ** 8)
+    assert np.all(c["A"][0] == 64 * L_tau * L ** 3) and np.all(c["B"][0] == 64 * L_tau * L ** 3)
+    obs = overlaps.observables(c, L, L_tau, 1)
+    assert abs(obs["F"][0]) < 1e-9 and abs(obs["Q2"][0] - L ** 4) < 1e-9
+    # Qt(tau1, tau) = Qt(tau1 + tau, L_tau - tau): sums over tau1 agree
+    for tau in range(1, L_tau):
+        assert np.array_equal(c["q2"][:, tau], c["q2"][:, L_tau - tau])
+        assert np.array_equal(c["q4"][:, tau], c["q4"][:, L_tau - tau])
+        assert np.array_equal(c["A"][tau], c["A"][L_tau - tau])
+    # independent random spins: <Qt^2> = L^2 away from tau = 0
+    m = c["q2"][:, 1:].mean() / L_tau
+    assert abs(m - L * L) < 0.1 * L * L
