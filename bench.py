@@ -44,7 +44,7 @@ def required_blocks_per_word(lanes: int = 64) -> float:
     return sum(1.0 - (1.0 - 4.0 ** (-(k - 1))) ** lanes for k in range(1, 17))
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c2_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_plain_large_traffic.txt")
 KERNEL_SOURCES = ("paper_2402_03920_amd/csrc/qsg_kernels.hip",
                   "paper_2402_03920_amd/csrc/qsg_internal.h")
 
@@ -63,7 +63,7 @@ def measured_traffic(workload: str):
     committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a plain
     copy's counters), or None when that summary was taken on other kernel
     sources or another workload."""
-    if workload != "c2" or not os.path.exists(TRAFFIC_FILE):
+    if workload != "plain-large" or not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
     with open(TRAFFIC_FILE) as f:
@@ -86,15 +86,19 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--samples", type=int, default=64)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c6"],
-                    help="c2 (default): 64 samples, L=16, L_tau=128; c1: one sample, L=8, "
-                         "L_tau=32; c3: 256 uneven samples; c4: L=24, L_tau=2048, 128 samples; "
-                         "c6: the c2 shape with the paper's coupling ladder (PT over k)")
+    ap.add_argument("--workload", default="plain-large",
+                    choices=["plain-small", "plain-large", "uneven", "production", "k-ladder"],
+                    help="plain-large (default): 64 samples, L=16, L_tau=128, 32 Gammas; "
+                         "plain-small: one sample, L=8, L_tau=32; uneven: 256 samples of mixed "
+                         "shapes; production: L=24, L_tau=2048, 128 samples; k-ladder: the "
+                         "plain-large shape with the paper's coupling ladder (PT over k)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default colour-pass schedule instead of tuning it per shape")
     ap.add_argument("--cpu-sweeps", type=int, default=0,
                     help="oracle sweeps for the CPU baseline (0: about 15 s of work)")
+    ap.add_argument("--overlaps", action="store_true",
+                    help="time the Euclidean-time overlap measurement instead (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     return ap.parse_args()
@@ -124,6 +128,9 @@ def main():
               "(groups are independent; sharding them needs no communication)",
               file=sys.stderr)
         sys.exit(2)
+    if args.overlaps:
+        overlap_bench(args)
+        return
     import numpy as np
     import torch
 
@@ -132,7 +139,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = W.c2_plain_large(n_samples=args.samples) if args.workload == "c2" else \
+    wl = W.plain_large(n_samples=args.samples) if args.workload == "plain-large" else \
         W.ALL[args.workload]()
     pe = wl.pt_every
     upd_per_sweep = wl.spin_updates_per_sweep()
@@ -256,6 +263,58 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def overlap_bench(args):
+    """Time qsg_tau_overlaps on the bench workload's first sample: every slot,
+    16 tau values, after a few sweeps; the kernel is VALU-bound, about
+    12 L^2 instructions per (tau1, tau) pair and wave (64 replicas)."""
+    import numpy as np
+    import torch
+    import qsg_workloads as W
+    from paper_2402_03920_amd import qsg
+    torch.cuda.set_device(0)
+    g = W.plain_large(n_samples=1).groups[0]
+    taus = sorted(set(int(x) for x in np.unique(np.geomspace(1, g.L_tau - 1, 15).astype(int))) | {0})
+    import ctypes as C
+    t = np.ascontiguousarray(np.asarray(taus, dtype=np.uint32))
+    words = len(taus) * (128 + 2 * g.L)
+    with qsg.Ensemble([g], pt_every=10, swaplog_cap=8) as ens:
+        ens.init_spins()
+        ens.sweep(20, qsg.QSG_BATCHED)
+        out = torch.zeros(words, dtype=torch.int64, device="cuda")
+        ptr = C.c_void_p(out.data_ptr())
+
+        def launch_all():  # one call per slot, enqueued back to back
+            for slot in range(len(g.gammas)):
+                rc = qsg.lib().qsg_tau_overlaps(ens.ctx, 0, slot, t.ctypes.data, len(taus), ptr, words)
+                if rc != qsg.QSG_OK:
+                    raise qsg.QSGError(rc, "tau overlaps")
+
+        launch_all()  # warm-up
+        ens.sync()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(ens.stream)
+        launch_all()
+        b.record(ens.stream)
+        torch.cuda.synchronize()
+        sec = a.elapsed_time(b) / 1e3
+    pairs = len(g.gammas) * len(taus) * g.L_tau
+    model = 12.0 * g.L * g.L * 64 * pairs  # lane-instructions
+    print(json.dumps({"metric": "tau-overlap measurement time", "value": round(sec * 1e3, 4),
+                      "unit": "ms per sample (all slots)", "higher_is_better": False,
+                      "config": {"workload": f"1 sample, L={g.L}, L_tau={g.L_tau}, "
+                                             f"{len(g.gammas)} slots, {len(taus)} tau values"},
+                      "us_per_slot_and_tau": round(sec * 1e6 / (len(g.gammas) * len(taus)), 3),
+                      "roofline": {"bound": "alu", "model": "12 L^2 VALU per (tau1, tau) pair "
+                                   "and wave of 64 replicas",
+                                   "achieved": round(model / sec / 1e12, 4),
+                                   "peak": round(PEAK_VALU_TOPS, 4),
+                                   "unit": "T VALU lane-instructions/s",
+                                   "frac": round(model / sec / 1e12 / PEAK_VALU_TOPS, 4)},
+                      "note": "HIP events around one launch per slot on the library's stream"}),
+          flush=True)
+
+
 def philox_ceiling(threads: int = 1 << 20, blocks: int = 2048, reps: int = 3):
     """Philox4x32-10 blocks per second of the whole GPU with nothing else in
     the way (the library's probe kernel: the colour pass's counter shape, one
@@ -310,15 +369,15 @@ def summarize(wl, ens):
 
 
 def describe(wl, name):
-    if name == "c2":
+    if name == "plain-large":
         return (f"{len(wl.groups)} samples x 64 replicas, L=16, L_tau=128, beta=8, "
                 f"32 Gammas geometric in [2,4], PT every {wl.pt_every} sweeps")
-    if name == "c1":
+    if name == "plain-small":
         return "1 sample x 64 replicas, L=8, L_tau=32, beta=4, 16 Gammas in [1.5,4.5]"
-    if name == "c6":
+    if name == "k-ladder":
         return (f"{len(wl.groups)} samples x 64 replicas, L=16, L_tau=128, one coupling k on "
                 f"every bond, 32 k in [0.25,0.33], PT over k every {wl.pt_every} sweeps")
-    if name == "c3":
+    if name == "uneven":
         return ("256 uneven samples x 64 replicas, L in {8..24}, L_tau in {64,128,256}, "
                 "beta=L_tau/16, 24-48 Gammas in [2,4]")
     return "2 groups x 64 samples, L=24, L_tau=2048, beta=128, 48 Gammas in [2.8,3.6]"

@@ -1,7 +1,7 @@
 """Train the ladder MLP on acceptance measured in plain runs, then compare
 learned and geometric ladders on fresh samples.
 
-    python -m paper_2402_03920_amd.learn_ladder --out gpurun_out/ladder.json
+    python -m paper_2402_03920_amd.learn_ladder --out ladder.json
 
 Training data: every group of the small plain workload (one sample), of the
 large plain workload (64 samples) and of the uneven ensemble (256 samples)
@@ -116,7 +116,7 @@ def main(argv=None):
     ap.add_argument("--eval-samples", type=int, default=128)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--c3-samples", type=int, default=256)
+    ap.add_argument("--uneven-samples", type=int, default=256)
     ap.add_argument("--focus-sweeps", type=int, default=50000,
                     help="second, longer comparison on the samples whose learned ladder "
                          "passed the floor (0: skip)")
@@ -125,8 +125,8 @@ def main(argv=None):
     torch.cuda.set_device(0)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     t0 = time.time()
-    sets = [W.c1_plain_small().groups, W.c2_plain_large().groups,
-            W.c3_batched_uneven(args.c3_samples).groups]
+    sets = [W.plain_small().groups, W.plain_large().groups,
+            W.uneven_ensemble(args.uneven_samples).groups]
     Xs, Ts, Ls = [], [], []
     for gs in sets:
         X, T, L, _ = collect(gs, args.train_sweeps, log=log)
@@ -137,7 +137,7 @@ def main(argv=None):
     model = ladder.LadderMLP(seed=0, bf16=True)
     hist = model.fit(X, T, L, steps=args.steps, lr=args.lr, log_every=max(args.steps // 10, 1))
     log(f"[ladder] trained on {len(X)} runs: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
-    ev = W.c5_eval(n_samples=args.eval_samples).groups
+    ev = W.ladder_eval(n_samples=args.eval_samples).groups
     res = compare(model, ev, args.eval_sweeps, log=log)
     if args.focus_sweeps:
         keep = [g for g, a in zip(ev, res["predicted_acceptance"]) if a >= 0.2]

@@ -92,7 +92,7 @@ def _replicas(seed: int) -> List[int]:
     return [int(seed)] * 64
 
 
-def c1_plain_small() -> Workload:
+def plain_small() -> Workload:
     """One sample, L=8, L_tau=32, beta=4, 16 Gammas geometric in [1.5, 4.5],
     64 replicas in the lanes, 1000 sweeps, PT every 10, J seed 1, MC seed 42."""
     lad = geometric_ladder(1.5, 4.5, 16)
@@ -100,7 +100,7 @@ def c1_plain_small() -> Workload:
     return Workload("plain L=8 Ltau=32 NG=16 1 sample", [g], 1000, 10)
 
 
-def c2_plain_large(n_samples: int = 64) -> Workload:
+def plain_large(n_samples: int = 64) -> Workload:
     """64 samples (one group each, 64 replicas), L=16, L_tau=128, beta=8,
     32 Gammas geometric in [2, 4], J seeds 1..64, 10^4 sweeps, PT every 10."""
     lad = geometric_ladder(2.0, 4.0, 32)
@@ -109,7 +109,7 @@ def c2_plain_large(n_samples: int = 64) -> Workload:
     return Workload("plain L=16 Ltau=128 NG=32 64 samples", groups, 10_000, 10)
 
 
-def c3_manifest_rows(n: int = 256, seed: int = 3):
+def uneven_manifest_rows(n: int = 256, seed: int = 3):
     """Uneven ensemble: L ~ U{8,12,16,20,24}, L_tau ~ U{64,128,256},
     N_Gamma ~ U{24..48}, drawn by numpy PCG64(seed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -119,10 +119,10 @@ def c3_manifest_rows(n: int = 256, seed: int = 3):
     return [(int(a), int(b), int(c)) for a, b, c in zip(Ls, Lts, NGs)]
 
 
-def c3_batched_uneven(n_samples: int = 256) -> Workload:
+def uneven_ensemble(n_samples: int = 256) -> Workload:
     """256 samples of uneven shape, beta = L_tau/16, Gammas geometric in
     [2, 4], J seeds 1..256, 1000 sweeps, PT every 10."""
-    rows = c3_manifest_rows(256)[:n_samples]
+    rows = uneven_manifest_rows(256)[:n_samples]
     groups = []
     for i, (L, Lt, ng) in enumerate(rows):
         groups.append(Group(L, Lt, Lt / 16.0, geometric_ladder(2.0, 4.0, ng),
@@ -130,7 +130,7 @@ def c3_batched_uneven(n_samples: int = 256) -> Workload:
     return Workload("batched uneven 256 samples", groups, 1000, 10)
 
 
-def c4_production() -> Workload:
+def production() -> Workload:
     """L=24, L_tau=2048, beta=128, 128 samples packed one per lane in two
     groups (J seeds 1..64 and 65..128), 48 Gammas geometric in [2.8, 3.6],
     10^5 sweeps, PT every 10."""
@@ -141,17 +141,17 @@ def c4_production() -> Workload:
                     100_000, 10)
 
 
-def c5_eval_rows(n: int = 128, seed: int = 5):
+def ladder_eval_rows(n: int = 128, seed: int = 5):
     rng = np.random.Generator(np.random.PCG64(seed))
     return [int(x) for x in rng.choice(np.array([12, 16, 20, 24]), size=n)]
 
 
-def c5_eval(ladders: Sequence[np.ndarray] | None = None,
+def ladder_eval(ladders: Sequence[np.ndarray] | None = None,
             n_samples: int = 128) -> Workload:
     """Fresh samples for the learned-ladder evaluation: L in {12,16,20,24},
     L_tau=256, beta=16, 32 Gammas in [2, 4] (geometric unless `ladders`
     given), J seeds 10001.., 10^4 sweeps, PT every 10."""
-    Ls = c5_eval_rows(128)[:n_samples]
+    Ls = ladder_eval_rows(128)[:n_samples]
     groups = []
     for i, L in enumerate(Ls):
         lad = geometric_ladder(2.0, 4.0, 32) if ladders is None else np.asarray(
@@ -169,7 +169,7 @@ def linear_k_ladder(kmax: float, kmin: float, n: int) -> np.ndarray:
     return np.minimum.accumulate(lad)
 
 
-def c6_coupling_ladder(n_samples: int = 64) -> Workload:
+def coupling_ladder(n_samples: int = 64) -> Workload:
     """The paper's own parametrisation (one coupling k on every bond, PT over
     k): 64 samples (64 replicas each), L=16, L_tau=128, 32 couplings from
     0.33 down to 0.25 around the paper's k ~ 0.29, J seeds 1..64, 10^4
@@ -196,10 +196,10 @@ def tiny_group(L=4, L_tau=8, beta=1.0, n_gamma=3, gmin=0.5, gmax=2.0,
 
 
 ALL = {
-    "c1": c1_plain_small,
-    "c2": c2_plain_large,
-    "c3": c3_batched_uneven,
-    "c4": c4_production,
-    "c5": c5_eval,
-    "c6": c6_coupling_ladder,
+    "plain-small": plain_small,
+    "plain-large": plain_large,
+    "uneven": uneven_ensemble,
+    "production": production,
+    "ladder-eval": ladder_eval,
+    "k-ladder": coupling_ladder,
 }

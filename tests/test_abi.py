@@ -80,7 +80,7 @@ def test_host_tables_reject_bad_ladders():
 
 def _ladders():
     out = []
-    for g in W.c1_plain_small().groups:
+    for g in W.plain_small().groups:
         out.append((g.beta, g.L_tau, g.gammas))
     out.append((8.0, 128, W.geometric_ladder(2.0, 4.0, 32)))             # c2
     for Lt, ng in ((64, 24), (128, 37), (256, 48)):                        # c3 shapes
@@ -125,7 +125,7 @@ def test_host_k_tables_reject_bad_ladders():
 
 
 def _k_ladders():
-    return [W.c6_coupling_ladder(1).groups[0].gammas,            # 32 k in [0.25, 0.33]
+    return [W.coupling_ladder(1).groups[0].gammas,            # 32 k in [0.25, 0.33]
             W.linear_k_ladder(0.5, 0.2, 3),
             np.array([0.4, 0.4, 0.3, 0.05]),                       # equal pair
             np.array([2.5, 1e-3])]                                 # saturated and tiny k

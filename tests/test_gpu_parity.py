@@ -183,7 +183,7 @@ def test_maximum_slots_bit_exact():
 def test_k_ladder_workload_truncated_bit_exact():
     """Two samples of the k-ladder workload (L=16, L_tau=128, 32 k in
     [0.25, 0.33]), 20 sweeps with PT every 10."""
-    wl = W.c6_coupling_ladder(n_samples=2)
+    wl = W.coupling_ladder(n_samples=2)
     ogs = oracle_groups(wl.groups, 16)
     say("[parity] k-ladder workload oracle")
     for og in ogs:
@@ -212,10 +212,10 @@ def test_explicit_pt_step_and_no_pt_flag():
         compare_state(ens, ogs)
 
 
-def test_c1_plain_full_bit_exact():
+def test_plain_small_full_bit_exact():
     """One sample, L=8, L_tau=32, beta=4, 16 Gammas in [1.5, 4.5], 1000
     sweeps with PT every 10: spins, energies, swap log, walkers, round trips."""
-    wl = W.c1_plain_small()
+    wl = W.plain_small()
     say("[parity] c1 oracle 1000 sweeps")
     og = chain.OracleGroup.from_workload_group(wl.groups[0], log_cap=128)
     og.run(wl.sweeps, wl.pt_every, threads=16)
@@ -228,10 +228,10 @@ def test_c1_plain_full_bit_exact():
             assert int(og.acc.sum()) > 0
 
 
-def test_c2_shape_truncated_bit_exact():
+def test_plain_large_shape_truncated_bit_exact():
     """Two samples of the L=16, L_tau=128, 32-Gamma workload, 20 sweeps with
     PT every 10 (the oracle's budget); all state compared."""
-    wl = W.c2_plain_large(n_samples=2)
+    wl = W.plain_large(n_samples=2)
     ogs = oracle_groups(wl.groups, 16)
     say("[parity] c2 shape oracle")
     for og in ogs:
@@ -242,10 +242,10 @@ def test_c2_shape_truncated_bit_exact():
         compare_state(ens, ogs)
 
 
-def test_c3_uneven_groups_truncated_bit_exact():
+def test_uneven_groups_truncated_bit_exact():
     """The first uneven-ensemble groups (mixed L, L_tau, N_Gamma) batched in
     one launch per pass, 20 sweeps with PT every 10."""
-    wl = W.c3_batched_uneven(n_samples=256)
+    wl = W.uneven_ensemble(n_samples=256)
     pick = [g for g in wl.groups if g.L * g.L * g.L_tau * g.n_gamma <= 8 * 8 * 128 * 48][:3]
     pick += [wl.groups[0]] if wl.groups[0] not in pick else []
     ogs = oracle_groups(pick, 16)
@@ -258,11 +258,11 @@ def test_c3_uneven_groups_truncated_bit_exact():
         compare_state(ens, ogs)
 
 
-def test_c4_full_shape_sampled_slots():
+def test_production_shape_sampled_slots():
     """Production shape L=24, L_tau=2048, 48 Gammas, 128 samples in the lanes
     of two groups: two sweeps before the first PT step (slots evolve
     independently there), the oracle following sampled slots on their own."""
-    wl = W.c4_production()
+    wl = W.production()
     with qsg.Ensemble(wl.groups, pt_every=10, swaplog_cap=16) as ens:
         ens.init_spins()
         ens.sweep(2, qsg.QSG_BATCHED)
@@ -280,7 +280,7 @@ def test_c4_full_shape_sampled_slots():
 def test_modes_agree_on_uneven_ensemble():
     """Plain per-group launches, batched launches and graph replay give the
     same state on 24 uneven groups (no oracle: the three GPU paths)."""
-    wl = W.c3_batched_uneven(n_samples=24)
+    wl = W.uneven_ensemble(n_samples=24)
     states = {}
     for mode in MODES:
         with qsg.Ensemble(wl.groups, pt_every=10, swaplog_cap=8) as ens:
@@ -296,7 +296,7 @@ def test_every_schedule_gives_the_same_trajectory(split):
     """The colour-pass schedule (when undecided words are packed) only moves
     work between waves: the trajectory is identical for every value, per
     group and per ensemble."""
-    groups = small_groups() + W.c3_batched_uneven(n_samples=3).groups
+    groups = small_groups() + W.uneven_ensemble(n_samples=3).groups
     with qsg.Ensemble(groups, pt_every=5, swaplog_cap=8) as ref:
         ref.init_spins()
         ref.sweep(20, qsg.QSG_BATCHED)
@@ -308,10 +308,10 @@ def test_every_schedule_gives_the_same_trajectory(split):
         assert np.array_equal(ens.get_state(), want)
 
 
-def test_c3_full_ensemble_batched_equals_per_sample_launches():
+def test_uneven_full_ensemble_batched_equals_per_sample_launches():
     """All 256 uneven samples: one launch per pass over every sample (graph
     replay and fused chunks) against one launch per sample and pass."""
-    wl = W.c3_batched_uneven(n_samples=256)
+    wl = W.uneven_ensemble(n_samples=256)
     states = {}
     for mode in ("plain", "graph", "fused_graph"):
         say(f"[parity] c3 full ensemble, mode={mode}")
