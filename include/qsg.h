@@ -237,23 +237,26 @@ void qsg_destroy(qsg_ctx* ctx);
  * = Philox(ctr = in[6i..6i+3], key = in[6i+4..6i+5]).  Device pointers. */
 qsg_status qsg_philox(const uint32_t* d_in, uint32_t* d_out, uint32_t n, void* hip_stream);
 
-/* Euclidean-time overlaps of the configuration now in slot `slot` of group
- * `group` (App. E: the tau-dependent Q2, Q4 and F of `overlap_tau`).  With
+/* Euclidean-time overlaps of the configurations now in slots first_slot ..
+ * first_slot + n_slots - 1 of group `group`, one launch (App. E: the
+ * tau-dependent Q2, Q4 and F of `overlap_tau`).  For each slot, with
  * q_x = S(x,tau1) S(x,tau1+tau) (tau1 + tau modulo L_tau), Qt = sum_x q_x,
  * column sums C_x1 = sum over y of q and row sums R_x2 = sum over x of q,
  * adds for every tau = taus[i] (host array, i < n_taus <= 64, tau < L_tau):
  *   q2[a][i] += sum_tau1 Qt^2 and q4[a][i] += sum_tau1 Qt^4 for lane a,
  *   A[i][d] += sum over lanes and tau1 of sum_x1 C_x1 C_{x1+d}, B likewise
  *   with R (d < L, indices modulo L),
- * into d_out (device, caller-owned and caller-zeroed int64, laid out
- * q2 [64][n_taus], q4 [64][n_taus], A [n_taus][L], B [n_taus][L];
- * out_words >= n_taus * (128 + 2L)).  Then Q2(tau) = <q2>/L_tau,
+ * into d_out (device, caller-owned and caller-zeroed int64, per slot
+ * q2 [64][n_taus], q4 [64][n_taus], A [n_taus][L], B [n_taus][L], slots one
+ * after the other; out_words >= n_slots * n_taus * (128 + 2L)).  Then
+ * Q2(tau) = <q2>/L_tau,
  * Q4(tau) = <q4>/L_tau and F(tau) = sum_d (A+B)(d) cos(2 pi d/L) /
  * (2 * 64 * L_tau) per call.  Integer sums: exact, order-independent.
  * Needs L <= 32 (QSG_E_UNSUPPORTED otherwise).  Enqueued on the context's
  * stream; does not change the chain. */
-qsg_status qsg_tau_overlaps(qsg_ctx* ctx, uint32_t group, uint32_t slot, const uint32_t* taus,
-                            uint32_t n_taus, int64_t* d_out, size_t out_words);
+qsg_status qsg_tau_overlaps(qsg_ctx* ctx, uint32_t group, uint32_t first_slot, uint32_t n_slots,
+                            const uint32_t* taus, uint32_t n_taus, int64_t* d_out,
+                            size_t out_words);
 
 /* Random-number ceiling of the device (measurement only; the generator of
  * Sec. 2.1.1): thread i < n_threads generates `blocks` Philox4x32-10 blocks

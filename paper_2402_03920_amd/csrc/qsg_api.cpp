@@ -920,12 +920,15 @@ qsg_status qsg_philox(const uint32_t* d_in, uint32_t* d_out, uint32_t n, void* h
     return QSG_OK;
 }
 
-qsg_status qsg_tau_overlaps(qsg_ctx* c, uint32_t group, uint32_t slot, const uint32_t* taus,
-                            uint32_t n_taus, int64_t* d_out, size_t out_words) {
+qsg_status qsg_tau_overlaps(qsg_ctx* c, uint32_t group, uint32_t first_slot, uint32_t n_slots,
+                            const uint32_t* taus, uint32_t n_taus, int64_t* d_out,
+                            size_t out_words) {
     if (qsg_status st = check_ctx(c)) return st;
     if (group >= c->gd.size()) return fail(c, QSG_E_INVALID, "group %u out of range", group);
     const GroupDev& g = c->gd[group];
-    if (slot >= g.N) return fail(c, QSG_E_INVALID, "slot %u out of range", slot);
+    if (n_slots == 0 || first_slot >= g.N || n_slots > g.N - first_slot)
+        return fail(c, QSG_E_INVALID, "slots %u..%u out of range", first_slot,
+                    first_slot + n_slots);
     if (g.L > qsg::kOvMaxL)
         return fail(c, QSG_E_UNSUPPORTED, "tau overlaps need L <= %u", qsg::kOvMaxL);
     if (!taus || n_taus == 0 || n_taus > qsg::kOvMaxTaus)
@@ -936,11 +939,11 @@ qsg_status qsg_tau_overlaps(qsg_ctx* c, uint32_t group, uint32_t slot, const uin
         if (taus[i] >= g.Ltau) return fail(c, QSG_E_INVALID, "tau %u >= L_tau", taus[i]);
         tl.t[i] = taus[i];
     }
-    const size_t need = (size_t)n_taus * (2 * 64 + 2 * g.L);
+    const size_t need = (size_t)n_slots * n_taus * (2 * 64 + 2 * g.L);
     if (!d_out) return fail(c, QSG_E_INVALID, "output is null");
     if (out_words < need) return fail(c, QSG_E_BUFFER, "output needs %zu int64", need);
-    QSG_HIP(c, qsg::launch_tau_overlaps(g.spins + (size_t)slot * g.V, g.L, g.Ltau, tl, d_out,
-                                        c->stream));
+    QSG_HIP(c, qsg::launch_tau_overlaps(g.spins + (size_t)first_slot * g.V, n_slots, g.L, g.Ltau,
+                                        tl, d_out, c->stream));
     return QSG_OK;
 }
 

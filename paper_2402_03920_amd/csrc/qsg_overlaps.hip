@@ -24,21 +24,27 @@ namespace {
 constexpr int kOvWaves = 4;  // waves (tau1 values) per block
 
 __global__ void __launch_bounds__(64 * kOvWaves)
-k_tau_overlaps(const uint64_t* __restrict__ S, uint32_t L, uint32_t Ltau, TauList taus,
-               int64_t* __restrict__ q2, int64_t* __restrict__ q4, int64_t* __restrict__ A,
-               int64_t* __restrict__ B) {
+k_tau_overlaps(const uint64_t* __restrict__ spins, uint32_t L, uint32_t Ltau, TauList taus,
+               int64_t* __restrict__ out) {
     __shared__ int32_t rows[kOvWaves][kOvMaxL][64];
     __shared__ int32_t cols[kOvWaves][kOvMaxL][64];
     __shared__ int32_t redA[kOvWaves][kOvMaxL];
     __shared__ int32_t redB[kOvWaves][kOvMaxL];
     __shared__ int64_t red2[kOvWaves][64], red4[kOvWaves][64];
+    // blockIdx.z: the slot, counted from the first one requested; each slot
+    // has its own output block q2 [64][n], q4 [64][n], A [n][L], B [n][L]
+    const uint32_t P = L * L;
+    const uint64_t* __restrict__ S = spins + (size_t)blockIdx.z * P * Ltau;
+    int64_t* __restrict__ q2 = out + (size_t)blockIdx.z * taus.n * (128 + 2 * L);
+    int64_t* __restrict__ q4 = q2 + 64 * (size_t)taus.n;
+    int64_t* __restrict__ A = q4 + 64 * (size_t)taus.n;
+    int64_t* __restrict__ B = A + (size_t)taus.n * L;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t i = blockIdx.y;
     const uint32_t tau = taus.t[i];
     const uint32_t tau1 = blockIdx.x * kOvWaves + w;
     const bool live = tau1 < Ltau;  // wave-uniform
-    const uint32_t P = L * L;
     int32_t C[kOvMaxL];
 #pragma unroll
     for (int x = 0; x < kOvMaxL; ++x) C[x] = 0;
@@ -124,16 +130,12 @@ k_tau_overlaps(const uint64_t* __restrict__ S, uint32_t L, uint32_t Ltau, TauLis
 
 }  // namespace
 
-hipError_t launch_tau_overlaps(const uint64_t* slot_spins, uint32_t L, uint32_t Ltau,
-                               const TauList& taus, int64_t* out, hipStream_t s) {
-    if (taus.n == 0) return hipSuccess;
-    int64_t* q2 = out;
-    int64_t* q4 = q2 + 64 * (size_t)taus.n;
-    int64_t* A = q4 + 64 * (size_t)taus.n;
-    int64_t* B = A + (size_t)taus.n * L;
-    const dim3 grid((Ltau + kOvWaves - 1) / kOvWaves, taus.n);
+hipError_t launch_tau_overlaps(const uint64_t* slot_spins, uint32_t n_slots, uint32_t L,
+                               uint32_t Ltau, const TauList& taus, int64_t* out, hipStream_t s) {
+    if (taus.n == 0 || n_slots == 0) return hipSuccess;
+    const dim3 grid((Ltau + kOvWaves - 1) / kOvWaves, taus.n, n_slots);
     hipLaunchKernelGGL(k_tau_overlaps, grid, dim3(64 * kOvWaves), 0, s, slot_spins, L, Ltau, taus,
-                       q2, q4, A, B);
+                       out);
     return hipGetLastError();
 }
 

@@ -101,8 +101,8 @@ _SIGS = {
     "qsg_destroy": (None, [C.c_void_p]),
     "qsg_philox": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
     "qsg_philox_probe": (C.c_int32, [C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p]),
-    "qsg_tau_overlaps": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint32,
-                                     C.c_void_p, C.c_size_t]),
+    "qsg_tau_overlaps": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p,
+                                     C.c_uint32, C.c_void_p, C.c_size_t]),
     "qsg_mlp_param_count": (C.c_uint32, []),
     "qsg_mlp_workspace_floats": (C.c_size_t, [C.c_uint32]),
     "qsg_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
@@ -265,24 +265,31 @@ class Ensemble:
             raise ValueError("ladder length differs from n_gamma")
         _check(lib().qsg_set_k_ladder(self.ctx, i, _ptr(k)), self.ctx)
 
-    def tau_overlaps(self, group: int, slot: int, taus) -> dict:
-        """Contributions of the configuration now in (group, slot) to the
-        Euclidean-time overlaps (qsg_tau_overlaps): int64 arrays q2, q4
-        [64][n_taus] and A, B [n_taus][L]; sum them over configurations and
-        pass the sums to tau_observables."""
+    def tau_overlaps(self, group: int, slots, taus) -> list:
+        """Contributions of the configurations now in (group, slots) to the
+        Euclidean-time overlaps (qsg_tau_overlaps, one launch): per slot a
+        dict of int64 arrays q2, q4 [64][n_taus] and A, B [n_taus][L]; sum
+        them over configurations and pass the sums to tau_observables.
+        `slots` is a slot index or a range of consecutive slots."""
         torch = self._torch
+        slots = range(slots, slots + 1) if isinstance(slots, int) else slots
+        if len(slots) == 0 or (len(slots) > 1 and slots.step != 1):
+            raise ValueError("slots must be consecutive")
         t = np.ascontiguousarray(np.asarray(taus, dtype=np.uint32))
         L = int(self.descs[group].L)
         n = t.size
-        words = n * (128 + 2 * L)
+        per = n * (128 + 2 * L)
+        words = per * len(slots)
         out = torch.zeros(words, dtype=torch.int64, device=self.workspace.device)
-        _check(lib().qsg_tau_overlaps(self.ctx, group, slot, _ptr(t), n,
+        _check(lib().qsg_tau_overlaps(self.ctx, group, slots[0], len(slots), _ptr(t), n,
                                       C.c_void_p(out.data_ptr()), words), self.ctx)
         self.sync()
-        a = out.cpu().numpy()
-        return {"q2": a[:64 * n].reshape(64, n), "q4": a[64 * n:128 * n].reshape(64, n),
-                "A": a[128 * n:128 * n + n * L].reshape(n, L),
-                "B": a[128 * n + n * L:].reshape(n, L)}
+        res = []
+        for a in out.cpu().numpy().reshape(len(slots), per):
+            res.append({"q2": a[:64 * n].reshape(64, n), "q4": a[64 * n:128 * n].reshape(64, n),
+                        "A": a[128 * n:128 * n + n * L].reshape(n, L),
+                        "B": a[128 * n + n * L:].reshape(n, L)})
+        return res
 
     def init_spins(self):
         _check(lib().qsg_init_spins(self.ctx), self.ctx)

@@ -406,20 +406,24 @@ def test_tau_overlaps_match_oracle():
             taus = sorted(set([0, 1, g.L_tau // 2, g.L_tau - 1]))
             spins = ens.get_spins(gi)
             V = g.L * g.L * g.L_tau
+            every = ens.tau_overlaps(gi, range(len(g.gammas)), taus)  # one launch
             for slot in range(len(g.gammas)):
-                got = ens.tau_overlaps(gi, slot, taus)
+                one = ens.tau_overlaps(gi, slot, taus)[0]
                 want = overlaps.contributions(spins[slot * V:(slot + 1) * V], g.L, g.L_tau, taus)
                 for key in ("q2", "q4", "A", "B"):
-                    assert np.array_equal(got[key], want[key]), (gi, slot, key)
+                    assert np.array_equal(one[key], want[key]), (gi, slot, key)
+                    assert np.array_equal(every[slot][key], want[key]), (gi, slot, key)
         # observables from two configurations
         g = groups[0]
         taus = list(range(g.L_tau))
-        acc = ens.tau_overlaps(0, 1, taus)
+        acc = ens.tau_overlaps(0, 1, taus)[0]
         ens.sweep(3, qsg.QSG_BATCHED)
-        more = ens.tau_overlaps(0, 1, taus)
+        more = ens.tau_overlaps(0, 1, taus)[0]
         acc = {k: acc[k] + more[k] for k in acc}
         obs = qsg.tau_observables(acc, g.L, g.L_tau, 2)
         assert abs(obs["Q2"][0] - g.L ** 4) < 1e-9 and abs(obs["F"][0]) < 1e-6
         assert np.allclose(obs["Q2"][1:], obs["Q2"][1:][::-1])
         with pytest.raises(qsg.QSGError):
             ens.tau_overlaps(0, 0, [g.L_tau])
+        with pytest.raises(qsg.QSGError):
+            ens.tau_overlaps(0, range(2, 4), [1])  # slots past the ladder
