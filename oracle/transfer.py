@@ -1,0 +1,139 @@
+"""Transfer matrix of the Trotter-Suzuki form in its parity sectors (test oracle).
+
+TEST INFRASTRUCTURE ONLY: used by the tests and the bench's CPU baseline,
+never by the product.
+
+Paper: Sec. 2.2 (the EDQSG code: the transfer matrix, the matrix-free
+product in three phases, the XOR-stride rounds) and App. D (the
+parity-aware basis).
+For an L x L slice with couplings J and the two couplings of the Trotter
+form (space k, time kp; the paper's equal-coupling form is kp = k):
+
+    T = W B W,   W = diag exp(k Bsp(S) / 2),
+    B = prod_sites (jp 1 + jm sigma^X_j),   jp = e^kp / (e^kp + e^-kp),
+                                            jm = e^-kp / (e^kp + e^-kp),
+
+i.e. T[S, S'] = e^{k Bsp(S)/2} prod_j (jp if S_j = S'_j else jm) e^{k Bsp(S')/2},
+the classical slice transfer matrix divided by (2 cosh kp)^(L^2).  Bsp(S)
+is the sum over the 2 L^2 bonds (site, +x) and (site, +y) of J S S'
+(site j = x1 + L x2; bit j of a state index set means S_j = -1).
+
+The parity P = prod_j sigma^X_j commutes with T.  With n an (L^2 - 1)-bit
+index (the last site's spin fixed to +1), the sector bases are
+|n>_e,o = (|n> +- |~n>) / sqrt(2), ~n the complement of all L^2 bits.  On
+them W acts as on |n>, sigma^X_j (j < L^2 - 1) maps n to n ^ 2^j, and the
+last site's sigma^X maps n to +-(its complement in L^2 - 1 bits), the sign
+being the sector's.  `apply` is that product, written in the paper's order:
+W, the rounds j = 0 .. L^2 - 2, the last site's round, W.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Tuple
+
+import numpy as np
+
+
+def couplings(kp: float) -> Tuple[float, float]:
+    """(jp, jm) of one site's factor jp 1 + jm sigma^X."""
+    ep, em = math.exp(kp), math.exp(-kp)
+    return ep / (ep + em), em / (ep + em)
+
+
+def slice_bond_sum(idx: np.ndarray, L: int, jx, jy) -> np.ndarray:
+    """Bsp of the slice states with the given indices (bit j <=> S_j = -1),
+    summed bond by bond from the definition."""
+    jx = np.asarray(jx, dtype=np.int64).reshape(L, L)  # [x2][x1]
+    jy = np.asarray(jy, dtype=np.int64).reshape(L, L)
+    idx = np.asarray(idx, dtype=np.int64)
+    B = np.zeros(idx.shape, dtype=np.int64)
+
+    def spin(x1, x2):
+        return 1 - 2 * ((idx >> (x1 + L * x2)) & 1)
+
+    for x2 in range(L):
+        for x1 in range(L):
+            s = spin(x1, x2)
+            B += jx[x2, x1] * s * spin((x1 + 1) % L, x2)
+            B += jy[x2, x1] * s * spin(x1, (x2 + 1) % L)
+    return B
+
+
+def sector_dim(L: int) -> int:
+    return 1 << (L * L - 1)
+
+
+def weights(L: int, k: float, jx, jy) -> np.ndarray:
+    """Diagonal of W on the sector basis: exp(k Bsp(n) / 2), n < 2^(L^2-1)."""
+    B = slice_bond_sum(np.arange(sector_dim(L), dtype=np.int64), L, jx, jy)
+    return np.exp(0.5 * k * B.astype(np.float64))
+
+
+def apply(L: int, k: float, kp: float, jx, jy, parity: int, x: np.ndarray,
+          w: np.ndarray | None = None) -> np.ndarray:
+    """T x in the sector of the given parity (+1 even, -1 odd), float64."""
+    assert parity in (1, -1)
+    n = L * L - 1
+    N = 1 << n
+    x = np.asarray(x, dtype=np.float64)
+    assert x.shape == (N,)
+    if w is None:
+        w = weights(L, k, jx, jy)
+    jp, jm = couplings(kp)
+    idx = np.arange(N, dtype=np.int64)
+    psi = w * x                                       # initialisation: W
+    for j in range(n):                                # rounds: sigma^X_j, j < L^2 - 1
+        psi = jp * psi + jm * psi[idx ^ (1 << j)]
+    comp = (N - 1) - idx                              # last site: complement of n bits
+    psi = jp * psi + parity * jm * psi[comp]
+    return w * psi                                    # finalisation: W
+
+
+def sector_matrix(L: int, k: float, kp: float, jx, jy, parity: int) -> np.ndarray:
+    """Dense sector matrix, column by column from `apply` (small L only)."""
+    N = sector_dim(L)
+    assert N <= 4096
+    w = weights(L, k, jx, jy)
+    cols = [apply(L, k, kp, jx, jy, parity, e, w) for e in np.eye(N)]
+    return np.array(cols).T
+
+
+def full_matrix(L: int, k: float, kp: float, jx, jy) -> np.ndarray:
+    """T on all 2^(L^2) slice states, from its matrix elements (small L only):
+    e^{k Bsp(S)/2} prod_j (jp if S_j = S'_j else jm) e^{k Bsp(S')/2}."""
+    V = L * L
+    assert V <= 12
+    idx = np.arange(1 << V, dtype=np.int64)
+    w = np.exp(0.5 * k * slice_bond_sum(idx, L, jx, jy).astype(np.float64))
+    jp, jm = couplings(kp)
+    diff = idx[:, None] ^ idx[None, :]
+    nd = np.zeros(diff.shape, dtype=np.int64)
+    for j in range(V):
+        nd += (diff >> j) & 1
+    return w[:, None] * (jp ** (V - nd)) * (jm ** nd) * w[None, :]
+
+
+def leading_eigenpairs(L: int, k: float, kp: float, jx, jy, parity: int,
+                       n_eig: int = 2) -> Dict[str, np.ndarray]:
+    """The n_eig largest eigenvalues of a sector (descending) and the
+    leading eigenvector: dense for L <= 3, ARPACK on `apply` above."""
+    N = sector_dim(L)
+    if N <= 4096:
+        vals, vecs = np.linalg.eigh(sector_matrix(L, k, kp, jx, jy, parity))
+        order = np.argsort(vals)[::-1]
+        return {"values": vals[order[:n_eig]], "vector": vecs[:, order[0]]}
+    from scipy.sparse.linalg import LinearOperator, eigsh
+    w = weights(L, k, jx, jy)
+    op = LinearOperator((N, N), matvec=lambda v: apply(L, k, kp, jx, jy, parity, np.ravel(v), w),
+                        dtype=np.float64)
+    vals, vecs = eigsh(op, k=n_eig, which="LA", tol=1e-13)
+    order = np.argsort(vals)[::-1]
+    return {"values": vals[order], "vector": vecs[:, order[0]]}
+
+
+def abs_bound(L: int, k: float, kp: float, jx, jy, x: np.ndarray) -> np.ndarray:
+    """|W| |B| |W| |x| elementwise: the even-sector product of |x| with every
+    factor's entries taken by absolute value (all of them are positive, so
+    this is `apply` with parity +1), the scale of the rounding error of
+    any evaluation order of T x."""
+    return apply(L, k, kp, jx, jy, 1, np.abs(np.asarray(x, dtype=np.float64)))
