@@ -99,6 +99,9 @@ def parse():
                     help="oracle sweeps for the CPU baseline (0: about 15 s of work)")
     ap.add_argument("--overlaps", action="store_true",
                     help="time the Euclidean-time overlap measurement instead (one JSON line)")
+    ap.add_argument("--transfer", action="store_true",
+                    help="time the transfer-matrix product (L = 5 sector) and a Lanczos solve "
+                         "instead (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     return ap.parse_args()
@@ -130,6 +133,9 @@ def main():
         sys.exit(2)
     if args.overlaps:
         overlap_bench(args)
+        return
+    if args.transfer:
+        transfer_bench(args)
         return
     import numpy as np
     import torch
@@ -313,6 +319,74 @@ def overlap_bench(args):
                                    "frac": round(model / sec / 1e12 / PEAK_VALU_TOPS, 4)},
                       "note": "HIP events around one launch over all slots on the library's stream"}),
           flush=True)
+
+
+def transfer_bench(args):
+    """Time the transfer-matrix product of one L = 5 slice in the even sector
+    (2^24 doubles; three passes, each reading and writing the vector once)
+    with HIP events around `steps` back-to-back products on one stream, and
+    one Lanczos solve for the two largest even eigenvalues.  Algorithmic HBM
+    traffic of a product: the input read once and the output written once,
+    16 B per sector state."""
+    import numpy as np
+    import torch
+    import qsg_workloads as W
+    from paper_2402_03920_amd import qsg
+    torch.cuda.set_device(0)
+    case = W.transfer_case()
+    N = qsg.tm_dim(case.L)
+    d = qsg.tm_desc(case.L, case.k, case.k_perp, case.jx, case.jy, 1)
+    x = torch.from_numpy(case.vector(0)).cuda()
+    y = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    reps = max(args.steps, 10)
+    for _ in range(max(args.warmup, 1)):
+        qsg.tm_apply(d, x, y, s)
+    s.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        qsg.tm_apply(d, x, y, s)
+    b.record(s)
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3 / reps
+    alg = 16.0 * N
+    t0 = time.perf_counter()
+    lz = qsg.tm_lanczos(d, 300, 2, 1e-9, seed=5, stream=s)
+    lanczos_s = time.perf_counter() - t0
+    result = {"metric": "transfer-matrix product time", "value": round(sec * 1e6, 3),
+              "unit": "us per product", "higher_is_better": False, "steps": reps,
+              "dtype": "f64", "data": "synthetic",
+              "config": {"workload": f"transfer-l5: L={case.L} slice, even sector of 2^24 states, "
+                                     f"k = k_perp = {case.k}, J = +-1 seed {case.seed}"},
+              "roofline": {"bound": "hbm", "kernel": "k_tm_first + k_tm_pass x2 (one product)",
+                           "achieved": round(alg / sec / 1e9, 2), "peak": 8000.0,
+                           "unit": "GB/s", "frac": round(alg / sec / 8e12, 4), "traffic": None,
+                           "algorithmic_bytes_per_product": int(alg),
+                           "layout_bytes_per_product": int(3 * alg),
+                           "layout_GBps": round(3 * alg / sec / 1e9, 2)},
+              "lanczos": {"eigenvalues": [float(v) for v in lz["values"]],
+                          "residual_estimates": [float(v) for v in lz["resid"]],
+                          "steps": lz["iters"], "seconds": round(lanczos_s, 3),
+                          "note": "two largest even eigenvalues, residual <= 1e-9 |lambda|, full "
+                                  "reorthogonalisation"},
+              "note": "HIP events around back-to-back products on one stream"}
+    if not args.no_cpu_baseline:
+        from oracle import transfer
+        t0 = time.perf_counter()
+        w = transfer.weights(case.L, case.k, case.jx, case.jy)
+        tw = time.perf_counter() - t0
+        xs = case.vector(0)
+        t0 = time.perf_counter()
+        transfer.apply(case.L, case.k, case.k_perp, case.jx, case.jy, 1, xs, w)
+        ta = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(ta * 1e6, 1), "unit": "us per product",
+                                  "cores": 1, "kind": "oracle",
+                                  "sample": "one even-sector product of the same slice "
+                                            f"(numpy, weights precomputed in {tw:.1f} s)",
+                                  "host_cpu": host_cpu()}
+    print(json.dumps(result), flush=True)
 
 
 def philox_ceiling(threads: int = 1 << 20, blocks: int = 2048, reps: int = 3):

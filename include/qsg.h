@@ -269,6 +269,67 @@ qsg_status qsg_philox_probe(uint32_t n_threads, uint32_t blocks, uint64_t key, u
                             void* hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Transfer matrix of one L x L slice in a parity sector (paper: Sec. 2.2,
+ * the EDQSG code and its matrix-free product; App. D, the parity-aware
+ * basis), float64:
+ *   T = W B W,  W = diag exp(k Bsp(n) / 2),
+ *   B = prod over the L^2 sites of (jp 1 + jm sigma^X),
+ *   jp = e^kp / (e^kp + e^-kp), jm = e^-kp / (e^kp + e^-kp),
+ * i.e. the slice transfer matrix of the Trotter-Suzuki form (weight
+ * exp(k Bsp + kp Bt) per prism configuration) divided by (2 cosh kp)^(L^2);
+ * the paper's equal-coupling form is kp = k.  Sector vectors have
+ * qsg_tm_dim(L) = 2^(L^2-1) doubles: entry n is the basis state
+ * (|n> + parity |~n>) / sqrt(2), n the spins of sites 0 .. L^2-2 (site
+ * j = x1 + L x2, bit j set <=> S_j = -1, the last site +1), ~n the complement
+ * of all L^2 bits.  Bsp(n) sums J S S' over the bonds (j, +x) and (j, +y),
+ * periodic.  One GPU holds L <= 5 (2^24 doubles per vector); larger L
+ * returns QSG_E_UNSUPPORTED.
+ * ---------------------------------------------------------------------- */
+#define QSG_TM_MAX_L 5
+
+typedef struct {
+    uint32_t L;       /* 2 .. QSG_TM_MAX_L */
+    int32_t parity;   /* +1 even sector, -1 odd sector */
+    double k;         /* space coupling (finite) */
+    double k_perp;    /* time coupling (finite) */
+    int8_t jx[QSG_TM_MAX_L * QSG_TM_MAX_L];  /* +-1: coupling of bond (j, +x), j < L*L */
+    int8_t jy[QSG_TM_MAX_L * QSG_TM_MAX_L];  /* +-1: coupling of bond (j, +y); rest ignored */
+} qsg_tm_desc;
+
+/* 2^(L^2-1), or 0 when L is outside 2 .. QSG_TM_MAX_L. */
+uint64_t qsg_tm_dim(uint32_t L);
+
+/* d_out = T d_in in the descriptor's sector: qsg_tm_dim(L) doubles each,
+ * device memory owned by the caller; d_in == d_out is allowed (other
+ * overlaps are not).  Enqueued on hip_stream (one to three kernels);
+ * QSG_E_INVALID for a bad descriptor or null pointer, QSG_E_UNSUPPORTED
+ * for L > QSG_TM_MAX_L, QSG_E_DEVICE if a launch fails; the message is
+ * qsg_last_error(NULL). */
+qsg_status qsg_tm_apply(const qsg_tm_desc* d, const double* d_in, double* d_out,
+                        void* hip_stream);
+
+/* Device workspace of qsg_tm_lanczos: (max_iter + 2) sector vectors plus
+ * small reduction buffers; 0 for an unsupported L or max_iter 0. */
+size_t qsg_tm_lanczos_workspace_bytes(uint32_t L, uint32_t max_iter);
+
+/* Largest eigenvalues of the sector's T by the Lanczos method (the paper
+ * leaves the iteration to a library; here it runs on the device with full
+ * reorthogonalisation, classical Gram-Schmidt applied twice, deterministic
+ * reductions).  Start vector: uniform [-1, 1) from splitmix64 of `seed`.
+ * Stops after max_iter steps, when the n_eig largest Ritz values all have
+ * residual estimates |beta_m y_m| <= tol * |largest|, or when the Krylov
+ * space is exhausted (then every Ritz value is exact).  Outputs (host):
+ * eigs[n_eig] descending, resid[n_eig] the residual estimates, *iters the
+ * steps taken; distinct Ritz values only (a multiple eigenvalue appears
+ * once), entries beyond the number found are NaN.  d_vec (device, may be
+ * NULL): the unit Ritz vector of eigs[0].  d_ws: qsg_tm_lanczos_workspace_
+ * bytes(L, max_iter) bytes, device, caller owned.  Synchronises hip_stream
+ * (every step reads two scalars back).  1 <= n_eig <= max_iter <= 4096. */
+qsg_status qsg_tm_lanczos(const qsg_tm_desc* d, uint32_t max_iter, uint32_t n_eig, double tol,
+                          uint64_t seed, void* d_ws, size_t ws_bytes, double* eigs,
+                          double* resid, uint32_t* iters, double* d_vec, void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Learned Gamma ladder: a 6 -> 128 -> 128 -> 128 -> 32 MLP (exact-erf GELU on
  * the hidden layers) mapping (L, L_tau, beta, frustrated-plaquette fraction,
  * Gamma_min, Gamma_max) features to 31 increment logits of log Gamma and a

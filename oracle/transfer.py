@@ -131,9 +131,11 @@ def leading_eigenpairs(L: int, k: float, kp: float, jx, jy, parity: int,
     return {"values": vals[order], "vector": vecs[:, order[0]]}
 
 
-def abs_bound(L: int, k: float, kp: float, jx, jy, x: np.ndarray) -> np.ndarray:
+def abs_bound(L: int, k: float, kp: float, jx, jy, x: np.ndarray,
+              w: np.ndarray | None = None) -> np.ndarray:
     """|W| |B| |W| |x| elementwise: the even-sector product of |x| with every
-    factor's entries taken by absolute value (all of them are positive, so
-    this is `apply` with parity +1), the scale of the rounding error of
-    any evaluation order of T x."""
-    return apply(L, k, kp, jx, jy, 1, np.abs(np.asarray(x, dtype=np.float64)))
+    factor's entries taken by absolute value (all of them are positive for
+    kp >= 0, so this is `apply` with parity +1), the scale of the rounding
+    error of any evaluation order of T x."""
+    assert kp >= 0
+    return apply(L, k, kp, jx, jy, 1, np.abs(np.asarray(x, dtype=np.float64)), w)

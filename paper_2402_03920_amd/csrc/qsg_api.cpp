@@ -1020,3 +1020,16 @@ qsg_status qsg_mlp_decode(const float* d_z, const double* d_gmin, const double* 
 }
 
 }  // extern "C"
+
+namespace qsg {
+// Failure of a context-free entry point: recorded for qsg_last_error(NULL).
+qsg_status report_error(qsg_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_create_error = buf;
+    return code;
+}
+}  // namespace qsg

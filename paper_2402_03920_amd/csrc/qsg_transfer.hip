@@ -1,0 +1,339 @@
+// Transfer matrix in a parity sector (paper: Sec. 2.2, the EDQSG product;
+// App. D, the parity-aware basis), float64:
+//
+//   out = W B W in,  W = diag exp(k Bsp(n) / 2),
+//   B = prod_{j < L^2-1} (jp + jm X_j) (jp + parity jm C),
+//
+// X_j flips bit j of the index, C complements all L^2 - 1 bits.  The factors
+// of B commute, so they are applied in whatever order suits the memory
+// layout: the complement round pairs tile t with its mirror tile and is done
+// in the first pass, next to the first W.
+//
+// Layout: a vector is 2^n doubles (n = L^2 - 1), index = sector state.  A
+// pass loads 4096 elements per block into registers (16 per thread), does
+// four rounds in registers, transposes through LDS, does the next three or
+// four rounds in registers and stores: every pass reads and writes the
+// vector once.  L = 5 takes three passes (bits 0-7 with W and the complement
+// round, 8-15, 16-23 with W), L = 4 two (0-7, 8-14), L <= 3 one small block.
+// W is not stored: each element's unsatisfied-bond count u comes from its
+// index with shifts, masks and two popcounts, and indexes a table of
+// exp(k (L^2 - u)) staged in LDS.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qsg_transfer.h"
+
+namespace qsg {
+namespace {
+
+constexpr int kTile = 4096;
+constexpr int kTmThreads = 256;
+
+// Unsatisfied bonds (site, +x) and (site, +y) of the slice state n: the
+// spins of the +x (+y) neighbours are n rotated within rows (columns).
+__device__ __forceinline__ uint32_t unsat(const TmParams& P, uint32_t n) {
+    const uint32_t nx = ((n >> 1) & P.not_last_col) | ((n << (P.L - 1)) & P.last_col);
+    const uint32_t ny = ((n >> P.L) & P.not_last_row) | ((n << (P.L * (P.L - 1))) & P.last_row);
+    return (uint32_t)__popc((n ^ nx ^ P.jxm) & P.all) + (uint32_t)__popc((n ^ ny ^ P.jym) & P.all);
+}
+
+__device__ __forceinline__ void stage_table(const TmParams& P, double* wt) {
+    for (uint32_t i = threadIdx.x; i < kTmTable; i += blockDim.x) wt[i] = P.wtab[i];
+}
+
+// The site factors of the bits of a register index: pairs (r, r | 2^q).
+template <int R>
+__device__ __forceinline__ void rounds(double (&x)[R], double jp, double jm) {
+#pragma unroll
+    for (int q = 1; q < R; q <<= 1) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r & q) continue;
+            const double a = x[r], b = x[r | q];
+            x[r] = jp * a + jm * b;
+            x[r | q] = jp * b + jm * a;
+        }
+    }
+}
+
+// Bits 4-7 of a 4096-element tile (index e = r + 16 hh + 256 c, register r
+// of thread (hh, c)): transpose through LDS so that each thread holds the 16
+// values of hh for one (r, c), four rounds, store.
+__device__ __forceinline__ void finish_low_tile(double* lds, double (&x)[16], size_t base,
+                                                uint32_t hh, uint32_t c, const TmParams& P,
+                                                double* out) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const uint32_t e = (uint32_t)r + 16 * hh + 256 * c;
+        lds[e + (e >> 4)] = x[r];
+    }
+    __syncthreads();
+    const uint32_t lo = threadIdx.x & 15, cc = threadIdx.x >> 4;
+    double y[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const uint32_t e = lo + 16 * (uint32_t)s + 256 * cc;
+        y[s] = lds[e + (e >> 4)];
+    }
+    rounds<16>(y, P.jp, P.jm);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) out[base + lo + 16 * (uint32_t)s + 256 * cc] = y[s];
+}
+
+// First pass (n >= 15): block b takes tile b and its mirror (indices
+// N-1-i), applies W, the last site's round between mirrored elements and
+// the rounds of bits 0-7 of both tiles.  in == out is allowed: every element
+// is read before any is written, and blocks touch disjoint tiles.
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_first(const TmParams P, const double* in, double* out) {
+    __shared__ double lds[kTile + kTile / 16];
+    __shared__ double wt[kTmTable];
+    stage_table(P, wt);
+    const size_t N = (size_t)1 << P.n;
+    const size_t base_a = (size_t)blockIdx.x * kTile;
+    const size_t base_b = N - kTile - base_a;
+    const uint32_t hh = threadIdx.x & 15, c = threadIdx.x >> 4;
+    // element r of this thread in tile A is e = r + 16 hh + 256 c; its
+    // mirror 4095 - e is element 15 - r of this thread in tile B
+    const uint32_t ea = 16 * hh + 256 * c;
+    const uint32_t eb = 16 * (15 - hh) + 256 * (15 - c);
+    double xa[16], xb[16];
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) {
+        const double2 va = *reinterpret_cast<const double2*>(in + base_a + ea + r);
+        const double2 vb = *reinterpret_cast<const double2*>(in + base_b + eb + r);
+        xa[r] = va.x;
+        xa[r + 1] = va.y;
+        xb[r] = vb.x;
+        xb[r + 1] = vb.y;
+    }
+    __syncthreads();  // table staged
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        xa[r] *= wt[unsat(P, (uint32_t)(base_a + ea) + (uint32_t)r)];
+        xb[r] *= wt[unsat(P, (uint32_t)(base_b + eb) + (uint32_t)r)];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const double a = xa[r], b = xb[15 - r];
+        xa[r] = P.jp * a + P.jm_last * b;
+        xb[15 - r] = P.jp * b + P.jm_last * a;
+    }
+    rounds<16>(xa, P.jp, P.jm);
+    rounds<16>(xb, P.jp, P.jm);
+    finish_low_tile(lds, xa, base_a, hh, c, P, out);
+    __syncthreads();  // LDS reused for the mirror tile
+    finish_low_tile(lds, xb, base_b, 15 - hh, 15 - c, P, out);
+}
+
+// A pass over bits b0 .. b0 + 3 + MB, in place.  The block's elements are
+// base + h 2^b0 + c, h < 2^(4+MB), c < C consecutive (C = 4096 / 2^(4+MB));
+// the block index fills the bits between log2 C and b0 and above the pass.
+// The last pass also applies W.
+template <int MB, bool kLast>
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_pass(const TmParams P, uint32_t b0, double* __restrict__ out) {
+    constexpr int M = 4 + MB;
+    constexpr int C = kTile >> M;
+    constexpr int LOGC = 12 - M;
+    constexpr int HB = 1 << MB;   // registers per group in the second half
+    constexpr int G = 16 / HB;    // groups per thread in the second half
+    constexpr int CP = C + 1;     // padded LDS row
+    __shared__ double lds[(1 << M) * CP];
+    __shared__ double wt[kTmTable];
+    if (kLast) stage_table(P, wt);
+    const uint32_t nlow = b0 - LOGC;
+    const size_t B = blockIdx.x;
+    const size_t base = ((B & ((1u << nlow) - 1)) << LOGC) | ((B >> nlow) << (b0 + M));
+    const size_t stride = (size_t)1 << b0;
+    const uint32_t t = threadIdx.x;
+    const uint32_t c = t % C, hh = t / C;
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = out[base + ((uint32_t)r + 16 * hh) * stride + c];
+    rounds<16>(x, P.jp, P.jm);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lds[((uint32_t)r + 16 * hh) * CP + c] = x[r];
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint32_t u = t + kTmThreads * (uint32_t)g;
+        const uint32_t cc = u % C, lo = u / C;
+        double y[HB];
+#pragma unroll
+        for (int s = 0; s < HB; ++s) y[s] = lds[(lo + 16 * (uint32_t)s) * CP + cc];
+        rounds<HB>(y, P.jp, P.jm);
+#pragma unroll
+        for (int s = 0; s < HB; ++s) {
+            const size_t i = base + (lo + 16 * (uint32_t)s) * stride + cc;
+            double v = y[s];
+            if (kLast) v *= wt[unsat(P, (uint32_t)i)];
+            out[i] = v;
+        }
+    }
+}
+
+// n <= 8: one block, one element per thread, every round through LDS in the
+// paper's order (W, bits 0 .. n-1, the last site, W).
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_small(const TmParams P, const double* in, double* out) {
+    __shared__ double v[kTmThreads];
+    __shared__ double wt[kTmTable];
+    stage_table(P, wt);
+    __syncthreads();
+    const uint32_t N = 1u << P.n, t = threadIdx.x;
+    const bool live = t < N;
+    double x = live ? in[t] * wt[unsat(P, t)] : 0.0;
+    for (uint32_t j = 0; j < P.n; ++j) {
+        if (live) v[t] = x;
+        __syncthreads();
+        if (live) x = P.jp * x + P.jm * v[t ^ (1u << j)];
+        __syncthreads();
+    }
+    if (live) v[t] = x;
+    __syncthreads();
+    if (live) out[t] = (P.jp * x + P.jm_last * v[N - 1 - t]) * wt[unsat(P, t)];
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos support: deterministic dot products (fixed partial-sum layout and
+// reduction order), updates, scaling, seeded start vectors.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const uint32_t w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (uint32_t i = 0; i < (blockDim.x >> 6); ++i) s += red[i];
+    return s;  // valid in thread 0
+}
+
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_dots(const double* __restrict__ V, size_t N, const double* __restrict__ w,
+          double* __restrict__ partial) {
+    __shared__ double red[kTmThreads / 64];
+    const double* __restrict__ v = V + (size_t)blockIdx.y * N;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kTmThreads + threadIdx.x; i < N;
+         i += (size_t)gridDim.x * kTmThreads)
+        acc += v[i] * w[i];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_reduce(const double* __restrict__ partial, uint32_t G, double* __restrict__ h) {
+    __shared__ double red[kTmThreads / 64];
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < G; i += kTmThreads) acc += partial[(size_t)blockIdx.x * G + i];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) h[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_update(const double* __restrict__ V, uint32_t nv, size_t N, const double* __restrict__ h,
+            double* __restrict__ w) {
+    for (size_t i = (size_t)blockIdx.x * kTmThreads + threadIdx.x; i < N;
+         i += (size_t)gridDim.x * kTmThreads) {
+        double acc = w[i];
+        for (uint32_t j = 0; j < nv; ++j) acc -= h[j] * V[(size_t)j * N + i];
+        w[i] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_scale(const double* __restrict__ w, size_t N, const double* __restrict__ nrm2,
+           double* __restrict__ v) {
+    const double inv = 1.0 / sqrt(nrm2[0]);
+    for (size_t i = (size_t)blockIdx.x * kTmThreads + threadIdx.x; i < N;
+         i += (size_t)gridDim.x * kTmThreads)
+        v[i] = w[i] * inv;
+}
+
+// splitmix64 (Steele, Lea and Flood, OOPSLA 2014) of seed + (i+1) * golden
+// gamma: 53 bits to a double in [-1, 1).
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_random(double* __restrict__ v, size_t N, uint64_t seed) {
+    for (size_t i = (size_t)blockIdx.x * kTmThreads + threadIdx.x; i < N;
+         i += (size_t)gridDim.x * kTmThreads) {
+        uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        v[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+}
+
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_combine(const double* __restrict__ V, uint32_t nv, size_t N, const double* __restrict__ y,
+             double* __restrict__ out) {
+    for (size_t i = (size_t)blockIdx.x * kTmThreads + threadIdx.x; i < N;
+         i += (size_t)gridDim.x * kTmThreads) {
+        double acc = 0.0;
+        for (uint32_t j = 0; j < nv; ++j) acc += y[j] * V[(size_t)j * N + i];
+        out[i] = acc;
+    }
+}
+
+uint32_t stream_blocks(size_t N) {
+    const size_t b = (N + kTmThreads - 1) / kTmThreads;
+    return (uint32_t)(b < 4096 ? b : 4096);
+}
+
+}  // namespace
+
+hipError_t launch_tm_apply(const TmParams& P, const double* in, double* out, hipStream_t s) {
+    if (P.n <= 8) {
+        hipLaunchKernelGGL(k_tm_small, dim3(1), dim3(kTmThreads), 0, s, P, in, out);
+        return hipGetLastError();
+    }
+    const size_t N = (size_t)1 << P.n;
+    hipLaunchKernelGGL(k_tm_first, dim3((uint32_t)(N / (2 * kTile))), dim3(kTmThreads), 0, s, P, in,
+                       out);
+    if (P.n == 15) {  // bits 8-14
+        hipLaunchKernelGGL((k_tm_pass<3, true>), dim3((uint32_t)(N / kTile)), dim3(kTmThreads), 0, s,
+                           P, 8u, out);
+    } else {          // n == 24: bits 8-15, then 16-23
+        hipLaunchKernelGGL((k_tm_pass<4, false>), dim3((uint32_t)(N / kTile)), dim3(kTmThreads), 0,
+                           s, P, 8u, out);
+        hipLaunchKernelGGL((k_tm_pass<4, true>), dim3((uint32_t)(N / kTile)), dim3(kTmThreads), 0, s,
+                           P, 16u, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tm_dots(const double* V, uint32_t nv, size_t N, const double* w, double* partial,
+                          double* h, hipStream_t s) {
+    hipLaunchKernelGGL(k_tm_dots, dim3(kTmDotBlocks, nv), dim3(kTmThreads), 0, s, V, N, w, partial);
+    hipLaunchKernelGGL(k_tm_reduce, dim3(nv), dim3(kTmThreads), 0, s, partial, kTmDotBlocks, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_tm_update(const double* V, uint32_t nv, size_t N, const double* h, double* w,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_tm_update, dim3(stream_blocks(N)), dim3(kTmThreads), 0, s, V, nv, N, h, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_tm_scale(const double* w, size_t N, const double* nrm2, double* v, hipStream_t s) {
+    hipLaunchKernelGGL(k_tm_scale, dim3(stream_blocks(N)), dim3(kTmThreads), 0, s, w, N, nrm2, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_tm_random(double* v, size_t N, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_tm_random, dim3(stream_blocks(N)), dim3(kTmThreads), 0, s, v, N, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_tm_combine(const double* V, uint32_t nv, size_t N, const double* y, double* out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_tm_combine, dim3(stream_blocks(N)), dim3(kTmThreads), 0, s, V, nv, N, y,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace qsg

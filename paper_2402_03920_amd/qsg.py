@@ -63,6 +63,15 @@ ROUNDTRIP_DTYPE = np.dtype([("state", "<u4"), ("t_last", "<u4"), ("count", "<u4"
                             ("pad", "<u4"), ("sum", "<u8")])
 
 
+TM_MAX_L = 5
+
+
+class qsg_tm_desc(C.Structure):
+    _fields_ = [("L", C.c_uint32), ("parity", C.c_int32), ("k", C.c_double),
+                ("k_perp", C.c_double), ("jx", C.c_int8 * (TM_MAX_L * TM_MAX_L)),
+                ("jy", C.c_int8 * (TM_MAX_L * TM_MAX_L))]
+
+
 class QSGError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"qsg error {code}: {msg}")
@@ -103,6 +112,12 @@ _SIGS = {
     "qsg_philox_probe": (C.c_int32, [C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p]),
     "qsg_tau_overlaps": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p,
                                      C.c_uint32, C.c_void_p, C.c_size_t]),
+    "qsg_tm_dim": (C.c_uint64, [C.c_uint32]),
+    "qsg_tm_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "qsg_tm_lanczos_workspace_bytes": (C.c_size_t, [C.c_uint32, C.c_uint32]),
+    "qsg_tm_lanczos": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_double, C.c_uint64,
+                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]),
     "qsg_mlp_param_count": (C.c_uint32, []),
     "qsg_mlp_workspace_floats": (C.c_size_t, [C.c_uint32]),
     "qsg_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
@@ -451,6 +466,63 @@ def philox_probe(out, n_threads: int, blocks: int, key: int, stream) -> None:
         raise ValueError("output tensor too small")
     _check(lib().qsg_philox_probe(n_threads, blocks, key, C.c_void_p(out.data_ptr()),
                                   C.c_void_p(stream.cuda_stream)))
+
+
+# ------------------------------------------------- transfer matrix (EDQSG)
+def tm_desc(L: int, k: float, k_perp: float, jx, jy, parity: int) -> qsg_tm_desc:
+    """Descriptor of the slice transfer matrix in one parity sector
+    (qsg_tm_apply): couplings jx, jy of +-1 per site j = x1 + L x2."""
+    d = qsg_tm_desc()
+    d.L, d.parity, d.k, d.k_perp = int(L), int(parity), float(k), float(k_perp)
+    jx = np.asarray(jx, dtype=np.int64).ravel()
+    jy = np.asarray(jy, dtype=np.int64).ravel()
+    if jx.size != L * L or jy.size != L * L:
+        raise ValueError("need L*L couplings per direction")
+    for j in range(L * L):
+        d.jx[j], d.jy[j] = int(jx[j]), int(jy[j])
+    return d
+
+
+def tm_dim(L: int) -> int:
+    return int(lib().qsg_tm_dim(L))
+
+
+def tm_apply(desc: qsg_tm_desc, x, out, stream=None) -> None:
+    """out = T x (float64 device tensors of tm_dim(L) entries; x may be out),
+    enqueued on `stream` (a torch stream; default the current one)."""
+    n = tm_dim(desc.L)
+    for t in (x, out):
+        if t.dtype != _torch_f64() or not t.is_cuda or t.numel() != n or not t.is_contiguous():
+            raise ValueError(f"need contiguous float64 device tensors of {n} entries")
+    sp = C.c_void_p(stream.cuda_stream) if stream is not None else _stream_ptr()
+    _check(lib().qsg_tm_apply(C.byref(desc), C.c_void_p(x.data_ptr()),
+                              C.c_void_p(out.data_ptr()), sp))
+
+
+def tm_lanczos(desc: qsg_tm_desc, max_iter: int, n_eig: int = 2, tol: float = 1e-10,
+               seed: int = 1, want_vector: bool = False, stream=None) -> dict:
+    """Largest eigenvalues of the sector (qsg_tm_lanczos): values
+    (descending), residual estimates, steps taken and, if asked, the unit
+    Ritz vector of the largest (a float64 device tensor)."""
+    import torch
+    nbytes = int(lib().qsg_tm_lanczos_workspace_bytes(desc.L, max_iter))
+    if nbytes == 0:
+        raise ValueError("unsupported L or max_iter")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    vec = torch.empty(tm_dim(desc.L), dtype=torch.float64, device="cuda") if want_vector else None
+    eigs = np.zeros(n_eig)
+    resid = np.zeros(n_eig)
+    iters = np.zeros(1, dtype=np.uint32)
+    sp = C.c_void_p(stream.cuda_stream) if stream is not None else _stream_ptr()
+    _check(lib().qsg_tm_lanczos(C.byref(desc), max_iter, n_eig, tol, seed,
+                                C.c_void_p(ws.data_ptr()), nbytes, _ptr(eigs), _ptr(resid),
+                                _ptr(iters), _dp(vec), sp))
+    return {"values": eigs, "resid": resid, "iters": int(iters[0]), "vector": vec}
+
+
+def _torch_f64():
+    import torch
+    return torch.float64
 
 
 # ------------------------------------------------------------- ladder MLP

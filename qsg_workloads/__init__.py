@@ -11,6 +11,11 @@ J = +-1 i.i.d. with p = 1/2 (paper: Sec. 1, Eq. (1); sample seeds of the
 input file, App. A), a ladder of transverse fields for parallel tempering
 (Sec. 2.1), and an update schedule of `pt_every` full sweeps per PT step
 (App. A, the "ptfr" field).
+
+The transfer-matrix product (Sec. 2.2) takes its couplings and vectors as
+plain inputs; `transfer_case` draws them here (numpy PCG64, J = +-1 with
+p = 1/2, vector entries standard normal), with the paper's EDQSG example
+coupling k = 0.31 in the equal-coupling form as the default.
 """
 from __future__ import annotations
 
@@ -203,3 +208,27 @@ ALL = {
     "ladder-eval": ladder_eval,
     "k-ladder": coupling_ladder,
 }
+
+
+@dataclass
+class TransferCase:
+    L: int
+    k: float
+    k_perp: float
+    jx: np.ndarray   # +-1 per site j = x1 + L x2, bond (j, +x)
+    jy: np.ndarray   # +-1 per site, bond (j, +y)
+    seed: int
+
+    def vector(self, stream: int = 0) -> np.ndarray:
+        """Standard-normal sector vector of 2^(L^2 - 1) doubles."""
+        rng = np.random.default_rng([self.seed, 1 + stream])
+        return rng.standard_normal(1 << (self.L * self.L - 1))
+
+
+def transfer_case(L: int = 5, k: float = 0.31, k_perp: float | None = None,
+                  seed: int = 6009) -> TransferCase:
+    """One disorder sample of an L x L slice for the transfer matrix."""
+    rng = np.random.default_rng(seed)
+    jx = 1 - 2 * rng.integers(0, 2, L * L)
+    jy = 1 - 2 * rng.integers(0, 2, L * L)
+    return TransferCase(L, float(k), float(k if k_perp is None else k_perp), jx, jy, seed)

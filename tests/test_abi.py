@@ -154,3 +154,38 @@ def test_tau_boundary_is_validated():
     d = _desc()
     d.reserved = 1
     assert _ws_bytes(d) == 0
+
+
+def test_transfer_matrix_sizes_and_validation_without_the_device():
+    """qsg_tm_dim / workspace sizes, and descriptor checks that fail before
+    any launch (L out of range, parity, couplings, null vectors)."""
+    from paper_2402_03920_amd import qsg
+    lib = qsg.lib()
+    assert [lib.qsg_tm_dim(L) for L in range(1, 8)] == [0, 8, 256, 1 << 15, 1 << 24, 0, 0]
+    assert lib.qsg_tm_lanczos_workspace_bytes(4, 0) == 0
+    assert lib.qsg_tm_lanczos_workspace_bytes(6, 10) == 0
+    n = lib.qsg_tm_lanczos_workspace_bytes(3, 10)
+    assert n >= 12 * 256 * 8 and n % 8 == 0
+    j = [1] * 9
+    dummy = C.c_void_p(1)  # never dereferenced: every case fails validation first
+    cases = [(qsg.tm_desc(3, 0.3, 0.3, j, j, 1), None, qsg.QSG_E_INVALID),
+             (qsg.tm_desc(3, 0.3, 0.3, j, j, 0), dummy, qsg.QSG_E_INVALID),
+             (qsg.tm_desc(3, 0.3, float("nan"), j, j, 1), dummy, qsg.QSG_E_INVALID),
+             (qsg.tm_desc(3, 0.3, 0.3, [1] * 8 + [0], j, 1), dummy, qsg.QSG_E_INVALID)]
+    big = qsg.tm_desc(5, 0.3, 0.3, [1] * 25, [1] * 25, 1)
+    big.L = 6
+    cases.append((big, dummy, qsg.QSG_E_UNSUPPORTED))
+    small = qsg.tm_desc(2, 0.3, 0.3, [1] * 4, [1] * 4, 1)
+    small.L = 1
+    cases.append((small, dummy, qsg.QSG_E_INVALID))
+    for d, ptr, want in cases:
+        rc = lib.qsg_tm_apply(C.byref(d), ptr, ptr, None)
+        assert rc == want, (d.L, d.parity, rc)
+        assert lib.qsg_last_error(None)
+    d = qsg.tm_desc(3, 0.3, 0.3, j, j, 1)
+    out = np.zeros(2)
+    it = np.zeros(1, dtype=np.uint32)
+    for max_iter, n_eig, ws in ((0, 1, 1 << 20), (10, 0, 1 << 20), (10, 11, 1 << 20), (10, 2, 8)):
+        rc = lib.qsg_tm_lanczos(C.byref(d), max_iter, n_eig, 1e-10, 1, dummy, ws, out.ctypes.data,
+                                out.ctypes.data, it.ctypes.data, None, None)
+        assert rc in (qsg.QSG_E_INVALID, qsg.QSG_E_BUFFER), (max_iter, n_eig, ws, rc)
