@@ -47,35 +47,44 @@ def required_blocks_per_word(lanes: int = 64) -> float:
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_plain_large_traffic.txt")
 KERNEL_SOURCES = ("paper_2402_03920_amd/csrc/qsg_kernels.hip",
                   "paper_2402_03920_amd/csrc/qsg_internal.h")
+TM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "transfer_l5_traffic.txt")
+TM_SOURCES = ("paper_2402_03920_amd/csrc/qsg_transfer.hip",
+              "paper_2402_03920_amd/csrc/qsg_transfer.h")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the colour pass on the bench workload, from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a plain
-    copy's counters), or None when that summary was taken on other kernel
-    sources or another workload."""
-    if workload != "plain-large" or not os.path.exists(TRAFFIC_FILE):
+def traffic_record(path: str, sources):
+    """Fields of a committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    (bytes scaled by a plain copy's counters), or None when it is missing or
+    was taken on other kernel sources."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
+    if vals.get("kernel_source_sha256") != kernel_source_hash(sources):
         return None
+    return vals
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the colour pass on the bench workload, or
+    None (another workload, or a summary of other kernel sources)."""
+    vals = traffic_record(TRAFFIC_FILE, KERNEL_SOURCES) if workload == "plain-large" else None
     try:
         return int(vals["fetch_bytes_per_launch"]) + int(vals["write_bytes_per_launch"])
-    except (KeyError, ValueError):
+    except (TypeError, KeyError, ValueError):
         return None
 
 
@@ -323,7 +332,7 @@ def overlap_bench(args):
 
 def transfer_bench(args):
     """Time the transfer-matrix product of one L = 5 slice in the even sector
-    (2^24 doubles; three passes, each reading and writing the vector once)
+    (2^24 doubles; two passes, each reading and writing the vector once)
     with HIP events around `steps` back-to-back products on one stream, and
     one Lanczos solve for the two largest even eigenvalues.  Algorithmic HBM
     traffic of a product: the input read once and the output written once,
@@ -352,6 +361,11 @@ def transfer_bench(args):
     torch.cuda.synchronize()
     sec = a.elapsed_time(b) / 1e3 / reps
     alg = 16.0 * N
+    rec = traffic_record(TM_TRAFFIC_FILE, TM_SOURCES)
+    try:
+        tm_traffic = int(rec["fetch_bytes_per_product"]) + int(rec["write_bytes_per_product"])
+    except (TypeError, KeyError, ValueError):
+        tm_traffic = None
     t0 = time.perf_counter()
     lz = qsg.tm_lanczos(d, 300, 2, 1e-9, seed=5, stream=s)
     lanczos_s = time.perf_counter() - t0
@@ -360,12 +374,15 @@ def transfer_bench(args):
               "dtype": "f64", "data": "synthetic",
               "config": {"workload": f"transfer-l5: L={case.L} slice, even sector of 2^24 states, "
                                      f"k = k_perp = {case.k}, J = +-1 seed {case.seed}"},
-              "roofline": {"bound": "hbm", "kernel": "k_tm_first + k_tm_pass x2 (one product)",
+              "roofline": {"bound": "hbm", "kernel": "k_tm_first<true> + k_tm_hi12 (one product)",
                            "achieved": round(alg / sec / 1e9, 2), "peak": 8000.0,
-                           "unit": "GB/s", "frac": round(alg / sec / 8e12, 4), "traffic": None,
+                           "unit": "GB/s", "frac": round(alg / sec / 8e12, 4),
+                           "traffic": tm_traffic,
+                           "traffic_unit": "HBM bytes per product (rocprofv3 FETCH_SIZE + "
+                                           "WRITE_SIZE of both passes, copy-calibrated)",
                            "algorithmic_bytes_per_product": int(alg),
-                           "layout_bytes_per_product": int(3 * alg),
-                           "layout_GBps": round(3 * alg / sec / 1e9, 2)},
+                           "layout_bytes_per_product": int(2 * alg),
+                           "layout_GBps": round(2 * alg / sec / 1e9, 2)},
               "lanczos": {"eigenvalues": [float(v) for v in lz["values"]],
                           "residual_estimates": [float(v) for v in lz["resid"]],
                           "steps": lz["iters"], "seconds": round(lanczos_s, 3),

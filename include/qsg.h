@@ -301,7 +301,7 @@ uint64_t qsg_tm_dim(uint32_t L);
 
 /* d_out = T d_in in the descriptor's sector: qsg_tm_dim(L) doubles each,
  * device memory owned by the caller; d_in == d_out is allowed (other
- * overlaps are not).  Enqueued on hip_stream (one to three kernels);
+ * overlaps are not).  Enqueued on hip_stream (one or two kernels);
  * QSG_E_INVALID for a bad descriptor or null pointer, QSG_E_UNSUPPORTED
  * for L > QSG_TM_MAX_L, QSG_E_DEVICE if a launch fails; the message is
  * qsg_last_error(NULL). */

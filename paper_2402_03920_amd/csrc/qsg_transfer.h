@@ -25,7 +25,7 @@ struct TmParams {
     double wtab[kTmTable];    // exp(k (L^2 - u)) = exp(k Bsp / 2), u unsatisfied bonds
 };
 
-// out = T in (in == out allowed).  Three launches for L = 5, two for L = 4,
+// out = T in (in == out allowed).  Two launches for L = 4 and L = 5,
 // one for L <= 3.
 hipError_t launch_tm_apply(const TmParams& P, const double* in, double* out, hipStream_t s);
 

@@ -10,11 +10,12 @@
 // in the first pass, next to the first W.
 //
 // Layout: a vector is 2^n doubles (n = L^2 - 1), index = sector state.  A
-// pass loads 4096 elements per block into registers (16 per thread), does
-// four rounds in registers, transposes through LDS, does the next three or
-// four rounds in registers and stores: every pass reads and writes the
-// vector once.  L = 5 takes three passes (bits 0-7 with W and the complement
-// round, 8-15, 16-23 with W), L = 4 two (0-7, 8-14), L <= 3 one small block.
+// pass loads a block of states into registers, does the rounds of a few
+// index bits in registers, transposes through LDS, does the next bits, and
+// stores: every pass reads and writes the vector once.  L = 5 takes two
+// passes (bits 0-11 with W and the complement round on 4096-state tiles;
+// bits 12-23 with W on 32768 states of 64-byte rows), L = 4 two (0-7,
+// 8-14), L <= 3 one small block.
 // W is not stored: each element's unsatisfied-bond count u comes from its
 // index with shifts, masks and two popcounts, and indexes a table of
 // exp(k (L^2 - u)) staged in LDS.
@@ -57,15 +58,17 @@ __device__ __forceinline__ void rounds(double (&x)[R], double jp, double jm) {
     }
 }
 
-// Bits 4-7 of a 4096-element tile (index e = r + 16 hh + 256 c, register r
-// of thread (hh, c)): transpose through LDS so that each thread holds the 16
-// values of hh for one (r, c), four rounds, store.
+// Bits 4-7 (and, with k12, 8-11) of a 4096-element tile whose bits 0-3 are
+// done: thread tt holds e = r + 16 tt in register r.  Transpose through LDS
+// so that each thread holds the 16 values of bits 4-7 for one (bits 0-3,
+// bits 8-11), four rounds; with k12 transpose again to bits 8-11, four more
+// rounds.  Stores are coalesced (consecutive threads, consecutive states).
+template <bool k12>
 __device__ __forceinline__ void finish_low_tile(double* lds, double (&x)[16], size_t base,
-                                                uint32_t hh, uint32_t c, const TmParams& P,
-                                                double* out) {
+                                                uint32_t tt, const TmParams& P, double* out) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const uint32_t e = (uint32_t)r + 16 * hh + 256 * c;
+        const uint32_t e = (uint32_t)r + 16 * tt;
         lds[e + (e >> 4)] = x[r];
     }
     __syncthreads();
@@ -77,14 +80,34 @@ __device__ __forceinline__ void finish_low_tile(double* lds, double (&x)[16], si
         y[s] = lds[e + (e >> 4)];
     }
     rounds<16>(y, P.jp, P.jm);
+    if (!k12) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) out[base + lo + 16 * (uint32_t)s + 256 * cc] = y[s];
+        for (int s = 0; s < 16; ++s) out[base + lo + 16 * (uint32_t)s + 256 * cc] = y[s];
+        return;
+    }
+    __syncthreads();  // every value read before the tile is rewritten
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const uint32_t e = lo + 16 * (uint32_t)s + 256 * cc;
+        lds[e + (e >> 4)] = y[s];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t e = threadIdx.x + 256 * (uint32_t)q;
+        y[q] = lds[e + (e >> 4)];
+    }
+    rounds<16>(y, P.jp, P.jm);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) out[base + threadIdx.x + 256 * (uint32_t)q] = y[q];
 }
 
 // First pass (n >= 15): block b takes tile b and its mirror (indices
 // N-1-i), applies W, the last site's round between mirrored elements and
-// the rounds of bits 0-7 of both tiles.  in == out is allowed: every element
-// is read before any is written, and blocks touch disjoint tiles.
+// the rounds of bits 0-7 (k12: 0-11) of both tiles.  in == out is allowed:
+// every element is read before any is written, and blocks touch disjoint
+// tiles.
+template <bool k12>
 __global__ void __launch_bounds__(kTmThreads)
 k_tm_first(const TmParams P, const double* in, double* out) {
     __shared__ double lds[kTile + kTile / 16];
@@ -93,11 +116,12 @@ k_tm_first(const TmParams P, const double* in, double* out) {
     const size_t N = (size_t)1 << P.n;
     const size_t base_a = (size_t)blockIdx.x * kTile;
     const size_t base_b = N - kTile - base_a;
-    const uint32_t hh = threadIdx.x & 15, c = threadIdx.x >> 4;
-    // element r of this thread in tile A is e = r + 16 hh + 256 c; its
-    // mirror 4095 - e is element 15 - r of this thread in tile B
-    const uint32_t ea = 16 * hh + 256 * c;
-    const uint32_t eb = 16 * (15 - hh) + 256 * (15 - c);
+    const uint32_t t = threadIdx.x;
+    // element r of this thread in tile A is e = r + 16 t; its mirror
+    // 4095 - e is element 15 - r of thread 255 - t's slot in tile B, which
+    // this thread loads
+    const uint32_t ea = 16 * t;
+    const uint32_t eb = 16 * (255 - t);
     double xa[16], xb[16];
 #pragma unroll
     for (int r = 0; r < 16; r += 2) {
@@ -122,9 +146,99 @@ k_tm_first(const TmParams P, const double* in, double* out) {
     }
     rounds<16>(xa, P.jp, P.jm);
     rounds<16>(xb, P.jp, P.jm);
-    finish_low_tile(lds, xa, base_a, hh, c, P, out);
+    finish_low_tile<k12>(lds, xa, base_a, t, P, out);
     __syncthreads();  // LDS reused for the mirror tile
-    finish_low_tile(lds, xb, base_b, 15 - hh, 15 - c, P, out);
+    finish_low_tile<k12>(lds, xb, base_b, 255 - t, P, out);
+}
+
+// Second pass of L = 5 (n = 24): bits 12-23 of the 32768 states
+// base + h 2^12 + c, h < 4096, c < 8 consecutive (64-byte rows), in place,
+// then W.  1024 threads hold 32 states each: bits 0-4 of h in registers,
+// then (transpose) bits 5-9, then (transpose) bits 10-11.  Each transpose
+// goes through 128 KiB of LDS in two halves (split by h bit 11, then bit 9);
+// the first uses rows h ^ ((h >> 5) & 3) so that neither side conflicts
+// on banks.  The grid (512 blocks) is a multiple of 16.
+constexpr int kHiThreads = 1024;
+constexpr int kHiCols = 8;
+
+__device__ __forceinline__ uint32_t hi_row_a(uint32_t h) {  // h < 4096, bit 11 = half
+    const uint32_t hp = h & 2047u;
+    return hp ^ ((hp >> 5) & 3u);
+}
+__device__ __forceinline__ uint32_t hi_row_b(uint32_t h) {  // bit 9 = half: removed
+    return (h & 511u) | ((h >> 10) << 9);
+}
+
+__global__ void __launch_bounds__(kHiThreads)
+k_tm_hi12(const TmParams P, double* __restrict__ out) {
+    __shared__ double lds[2048 * kHiCols];
+    __shared__ double wt[kTmTable];
+    stage_table(P, wt);
+    const uint32_t t = threadIdx.x;
+    const uint32_t c = t & 7u;
+    // Column blocks 2m and 2m+1 share every 128-byte line.  Workgroups are
+    // dealt to the eight XCDs in turn, so physical blocks p and p + 8 run on
+    // the same XCD at about the same time: give them the two halves, and the
+    // second half of each line comes from that XCD's L2.
+    const uint32_t p = blockIdx.x;
+    const uint32_t lb = 2 * (8 * (p >> 4) + (p & 7u)) + ((p >> 3) & 1u);
+    const size_t base = (size_t)lb * kHiCols;
+    double x[32];
+    // layout 1: h = r + 32 hb
+    const uint32_t hb = t >> 3;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) x[r] = out[base + ((size_t)((uint32_t)r + 32 * hb) << 12) + c];
+    rounds<32>(x, P.jp, P.jm);
+    // layout 2: h = hl + 32 s + 1024 hh, hl = bits 0-4, hh = bits 10-11
+    const uint32_t hl = (t >> 3) & 31u, hh = t >> 8;
+    const uint32_t half = t >> 9;  // h bit 11 in layouts 1 and 2
+#pragma unroll
+    for (uint32_t k = 0; k < 2; ++k) {
+        __syncthreads();
+        if (half == k) {
+#pragma unroll
+            for (int r = 0; r < 32; ++r)
+                lds[hi_row_a((uint32_t)r + 32 * hb) * kHiCols + c] = x[r];
+        }
+        __syncthreads();
+        if (half == k) {
+#pragma unroll
+            for (int s = 0; s < 32; ++s)
+                x[s] = lds[hi_row_a(hl + 32 * (uint32_t)s + 1024 * hh) * kHiCols + c];
+        }
+    }
+    rounds<32>(x, P.jp, P.jm);
+    // layout 3: h = hm + 128 g + 1024 q, register 4 g + q, hm = bits 0-6
+    const uint32_t hm = t >> 3;
+#pragma unroll
+    for (uint32_t k = 0; k < 2; ++k) {
+        __syncthreads();
+#pragma unroll
+        for (int s = 16 * k; s < 16 * (int)k + 16; ++s)
+            lds[hi_row_b(hl + 32 * (uint32_t)s + 1024 * hh) * kHiCols + c] = x[s];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t g = 4 * k + (uint32_t)(j >> 2), q = (uint32_t)(j & 3);
+            x[16 * k + j] = lds[hi_row_b(hm + 128 * g + 1024 * q) * kHiCols + c];
+        }
+    }
+#pragma unroll
+    for (int q = 1; q < 4; q <<= 1) {  // bits 10-11: register bits 0-1
+#pragma unroll
+        for (int r = 0; r < 32; ++r) {
+            if (r & q) continue;
+            const double a = x[r], b = x[r | q];
+            x[r] = P.jp * a + P.jm * b;
+            x[r | q] = P.jp * b + P.jm * a;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const uint32_t g = (uint32_t)(j >> 2), q = (uint32_t)(j & 3);
+        const size_t i = base + ((size_t)(hm + 128 * g + 1024 * q) << 12) + c;
+        out[i] = x[j] * wt[unsat(P, (uint32_t)i)];
+    }
 }
 
 // A pass over bits b0 .. b0 + 3 + MB, in place.  The block's elements are
@@ -292,16 +406,16 @@ hipError_t launch_tm_apply(const TmParams& P, const double* in, double* out, hip
         return hipGetLastError();
     }
     const size_t N = (size_t)1 << P.n;
-    hipLaunchKernelGGL(k_tm_first, dim3((uint32_t)(N / (2 * kTile))), dim3(kTmThreads), 0, s, P, in,
-                       out);
-    if (P.n == 15) {  // bits 8-14
+    if (P.n == 15) {  // bits 0-7, then 8-14
+        hipLaunchKernelGGL(k_tm_first<false>, dim3((uint32_t)(N / (2 * kTile))), dim3(kTmThreads), 0,
+                           s, P, in, out);
         hipLaunchKernelGGL((k_tm_pass<3, true>), dim3((uint32_t)(N / kTile)), dim3(kTmThreads), 0, s,
                            P, 8u, out);
-    } else {          // n == 24: bits 8-15, then 16-23
-        hipLaunchKernelGGL((k_tm_pass<4, false>), dim3((uint32_t)(N / kTile)), dim3(kTmThreads), 0,
-                           s, P, 8u, out);
-        hipLaunchKernelGGL((k_tm_pass<4, true>), dim3((uint32_t)(N / kTile)), dim3(kTmThreads), 0, s,
-                           P, 16u, out);
+    } else {          // n == 24: bits 0-11, then 12-23
+        hipLaunchKernelGGL(k_tm_first<true>, dim3((uint32_t)(N / (2 * kTile))), dim3(kTmThreads), 0,
+                           s, P, in, out);
+        hipLaunchKernelGGL(k_tm_hi12, dim3((uint32_t)(N / (4096 * kHiCols))), dim3(kHiThreads), 0, s,
+                           P, out);
     }
     return hipGetLastError();
 }
