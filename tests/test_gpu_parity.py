@@ -391,14 +391,17 @@ def test_state_does_not_depend_on_reused_memory():
 
 def test_tau_overlaps_match_oracle():
     """Euclidean-time overlaps (App. E) of live configurations, integer sums
-    compared exactly with the oracle on the same spins: ragged L_tau (blocks
-    of four slices), L = 32 (the largest supported), an antiperiodic prism,
-    repeated calls accumulating."""
+    compared exactly with the oracle on the same spins: ragged L_tau (several
+    blocks of 32 slices and a partial one), L = 32 (the largest supported),
+    L = 4, 6, 16, 24 (the kernel is instantiated per width), an antiperiodic
+    prism, repeated calls accumulating."""
     from oracle import overlaps
     groups = [W.tiny_group(L=6, L_tau=10, beta=2.0, n_gamma=3, group_id=40, per_lane=True,
                            j_seed=7),
               W.tiny_group(L=32, L_tau=4, beta=1.0, n_gamma=2, group_id=41),
-              W.tiny_group(L=4, L_tau=6, beta=1.5, n_gamma=2, group_id=42, antiperiodic=True)]
+              W.tiny_group(L=4, L_tau=6, beta=1.5, n_gamma=2, group_id=42, antiperiodic=True),
+              W.tiny_group(L=16, L_tau=70, beta=4.0, n_gamma=2, group_id=43),
+              W.tiny_group(L=24, L_tau=8, beta=1.0, n_gamma=3, group_id=44, per_lane=True)]
     with qsg.Ensemble(groups, pt_every=5, swaplog_cap=8) as ens:
         ens.init_spins()
         ens.sweep(7, qsg.QSG_BATCHED)
