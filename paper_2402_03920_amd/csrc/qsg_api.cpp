@@ -483,7 +483,7 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         g.hist = at<uint32_t>(c, gl.hist);
         c->gd.push_back(g);
         pre_sweep[i + 1] = pre_sweep[i] + g.N * qsg::sweep_blocks_per_slot(g.V);
-        pre_energy[i + 1] = pre_energy[i] + (g.N >= 2 ? g.N * qsg::energy_blocks_per_slot(g.V) : 0);
+        pre_energy[i + 1] = pre_energy[i] + (g.N >= 2 ? g.N * qsg::energy_blocks_per_slot(g.V, qsg::kEnergyWords) : 0);
         pre_swap[i + 1] = pre_swap[i] + (g.N >= 2 ? qsg::swap_blocks(g.V) : 0);
         pre_slots[i + 1] = pre_slots[i] + g.N;
         if (g.V > max_v) max_v = g.V;

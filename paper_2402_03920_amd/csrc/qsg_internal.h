@@ -132,12 +132,13 @@ hipError_t launch_swap_apply_batched(const BatchPlan& plan, hipStream_t s);
 
 // Blocks one group needs in each pass (host and device agree on these).
 __host__ __device__ inline uint32_t sweep_blocks_per_slot(uint32_t V);
-__host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V);
+__host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V, uint32_t words);
 __host__ __device__ inline uint32_t swap_blocks(uint32_t V);
 
 constexpr int kSweepBlock = 256;   // threads per block of a colour pass
 constexpr uint32_t kWaveSize = 64;
-constexpr int kEnergyWords = 32;   // words per thread in the energy pass
+constexpr int kEnergyWords = 64;   // words per thread, batched energy pass
+constexpr int kEnergyWordsSlot = 32;  // words per thread, energy pass of one group
 constexpr int kEnergyBlock = 256;
 constexpr int kSwapBlock = 256;
 
@@ -147,8 +148,8 @@ namespace qsg {
 __host__ __device__ inline uint32_t sweep_blocks_per_slot(uint32_t V) {
     return (V / 2 + kSweepBlock - 1) / kSweepBlock;
 }
-__host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V) {
-    const uint32_t per_block = kEnergyBlock * kEnergyWords;
+__host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V, uint32_t words) {
+    const uint32_t per_block = kEnergyBlock * words;
     return (V + per_block - 1) / per_block;
 }
 __host__ __device__ inline uint32_t swap_blocks(uint32_t V) {

@@ -553,8 +553,9 @@ k_chunk_fused(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ 
 // bonds and time bonds (each bond counted once, from its lower endpoint),
 // and per lane pair (2p, 2p+1) the number of sites where they differ.
 // Each thread adds its words into bit-sliced vertical counters; each wave
-// then turns counters into per-lane totals with ballots and adds them to
-// the slot's counters with integer atomics (order-independent, exact).
+// then turns counters into per-lane totals (a bit transpose across the wave
+// and popcounts) and adds them to the slot's counters with integer atomics
+// (order-independent, exact).
 // ---------------------------------------------------------------------------
 // Bit-sliced per-lane counter: value = ones + 2 twos + 4 fours + 8 * (hi as
 // a binary number).  Planes are added eight at a time with carry-save adders
@@ -600,30 +601,51 @@ __device__ __forceinline__ void add8(LaneCounter<NH>& c, const uint64_t (&x)[8])
     }
 }
 
-// Total of lane j over the wave (all 64 threads' counters), via ballots.
-template <int NH>
-__device__ __forceinline__ uint32_t lane_total(const LaneCounter<NH>& c, uint32_t j) {
-    uint32_t tot = (uint32_t)__popcll(__ballot((int)((c.ones >> j) & 1u))) +
-                   ((uint32_t)__popcll(__ballot((int)((c.twos >> j) & 1u))) << 1) +
-                   ((uint32_t)__popcll(__ballot((int)((c.fours >> j) & 1u))) << 2);
+// 64 x 64 bit transpose across the wave: afterwards thread t holds, in bit
+// b, bit t of thread b's word.  Stage s exchanges with thread t ^ s the bits
+// whose index differs from t in bit s (swapping bit s of the thread index
+// with bit s of the bit index); the six stages commute.
+__device__ __forceinline__ uint64_t wave_transpose(uint64_t x) {
+    const uint32_t t = threadIdx.x & 63u;
+    constexpr uint64_t kHigh[6] = {0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull,
+                                   0xF0F0F0F0F0F0F0F0ull, 0xFF00FF00FF00FF00ull,
+                                   0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
 #pragma unroll
-    for (int i = 0; i < NH; ++i)
-        tot += (uint32_t)__popcll(__ballot((int)((c.hi[i] >> j) & 1u))) << (3 + i);
+    for (int k = 5; k >= 0; --k) {
+        const uint32_t sh = 1u << k;
+        const uint64_t m = kHigh[k];  // bits b with b & sh set
+        const uint64_t y = lo_hi((uint32_t)__shfl_xor((int)(uint32_t)x, (int)sh, 64),
+                                 (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), (int)sh, 64));
+        x = (t & sh) ? ((x & m) | ((y & m) >> sh)) : ((x & ~m) | ((y & ~m) << sh));
+    }
+    return x;
+}
+
+// Per-lane totals over the wave's 64 threads of a bit-sliced counter: thread
+// t gets the total of lane t.
+template <int NH>
+__device__ __forceinline__ uint32_t lane_total(const LaneCounter<NH>& c) {
+    uint32_t tot = (uint32_t)__popcll(wave_transpose(c.ones)) +
+                   ((uint32_t)__popcll(wave_transpose(c.twos)) << 1) +
+                   ((uint32_t)__popcll(wave_transpose(c.fours)) << 2);
+#pragma unroll
+    for (int i = 0; i < NH; ++i) tot += (uint32_t)__popcll(wave_transpose(c.hi[i])) << (3 + i);
     return tot;
 }
 
+template <int kWords>
 __device__ __forceinline__ void energy_block(const GroupDev& G, uint32_t g, uint32_t blk,
                                              int32_t* __restrict__ cnt) {
-    static_assert(kEnergyWords % 8 == 0, "words come in chunks of eight");
+    static_assert(kWords % 8 == 0, "words come in chunks of eight");
     const uint32_t L = G.L, P = L * L, V = G.V;
     const uint64_t* __restrict__ S = G.spins + (size_t)g * V;
-    // per thread and lane at most 2*kEnergyWords unsatisfied space bonds and
-    // kEnergyWords time bonds or differing pairs
-    LaneCounter<counter_planes(2 * kEnergyWords)> Csp;
-    LaneCounter<counter_planes(kEnergyWords)> Ct, Cq;
-    const uint32_t first = blk * (kEnergyBlock * kEnergyWords) + threadIdx.x;
+    // per thread and lane at most 2*kWords unsatisfied space bonds and
+    // kWords time bonds or differing pairs
+    LaneCounter<counter_planes(2 * kWords)> Csp;
+    LaneCounter<counter_planes(kWords)> Ct, Cq;
+    const uint32_t first = blk * (kEnergyBlock * kWords) + threadIdx.x;
 #pragma unroll 1
-    for (int k0 = 0; k0 < kEnergyWords; k0 += 8) {
+    for (int k0 = 0; k0 < kWords; k0 += 8) {
         uint64_t xs[8], ys[8], ts[8], qs[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -651,27 +673,17 @@ __device__ __forceinline__ void energy_block(const GroupDev& G, uint32_t g, uint
         add8(Cq, qs);
     }
     const uint32_t lane = threadIdx.x & 63u;
-    uint32_t my_sp = 0, my_t = 0, my_q = 0;
-#pragma unroll 1
-    for (uint32_t j = 0; j < 64; ++j) {
-        const uint32_t a = lane_total(Csp, j);
-        const uint32_t b = lane_total(Ct, j);
-        if (lane == j) { my_sp = a; my_t = b; }
-    }
-#pragma unroll 1
-    for (uint32_t p = 0; p < 32; ++p) {
-        const uint32_t c = lane_total(Cq, 2 * p);
-        if (lane == p) my_q = c;
-    }
+    const uint32_t my_sp = lane_total(Csp), my_t = lane_total(Ct);
+    const uint32_t my_q = lane_total(Cq);  // pair p's total sits at lane 2p
     int32_t* __restrict__ c = cnt + g * kCntStride;
     if (my_sp) atomicAdd(&c[lane], (int32_t)my_sp);
     if (my_t) atomicAdd(&c[64 + lane], (int32_t)my_t);
-    if (lane < 32 && my_q) atomicAdd(&c[128 + lane], (int32_t)my_q);
+    if (!(lane & 1u) && my_q) atomicAdd(&c[128 + (lane >> 1)], (int32_t)my_q);
 }
 
 __global__ void __launch_bounds__(kEnergyBlock)
 k_energy(const GroupDev G, int32_t* cnt) {
-    energy_block(G, blockIdx.y, blockIdx.x, cnt);
+    energy_block<kEnergyWordsSlot>(G, blockIdx.y, blockIdx.x, cnt);
 }
 
 __global__ void __launch_bounds__(kEnergyBlock)
@@ -680,9 +692,9 @@ k_energy_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict
     const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
     const GroupDev G = uniform_record(groups + gi);
     const uint32_t local = blockIdx.x - prefix[gi];
-    const uint32_t nb = energy_blocks_per_slot(G.V);
+    const uint32_t nb = energy_blocks_per_slot(G.V, kEnergyWords);
     const uint32_t g = local / nb;
-    energy_block(G, g, local - g * nb, G.cnt);
+    energy_block<kEnergyWords>(G, g, local - g * nb, G.cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -948,8 +960,8 @@ hipError_t launch_half_sweep(const GroupDev& g, uint32_t colour, const uint32_t*
     return hipGetLastError();
 }
 hipError_t launch_energy(const GroupDev& g, int32_t* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy, dim3(energy_blocks_per_slot(g.V), g.N), dim3(kEnergyBlock), 0, s,
-                       g, cnt);
+    hipLaunchKernelGGL(k_energy, dim3(energy_blocks_per_slot(g.V, kEnergyWordsSlot), g.N),
+                       dim3(kEnergyBlock), 0, s, g, cnt);
     return hipGetLastError();
 }
 hipError_t launch_pt(const GroupDev& g, const uint32_t* ctr, uint32_t p_add, hipStream_t s) {
