@@ -15,10 +15,7 @@ from __future__ import annotations
 
 import json
 import os
-import time
-from typing import Dict, Iterable, List, Tuple
-
-import numpy as np
+from typing import Dict, Iterable, List
 
 from . import qsg
 

@@ -20,7 +20,6 @@ import math
 import sys
 import time
 from dataclasses import replace
-from typing import List
 
 import numpy as np
 

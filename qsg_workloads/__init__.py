@@ -19,7 +19,7 @@ coupling k = 0.31 in the equal-coupling form as the default.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import List, Sequence
 
 import numpy as np

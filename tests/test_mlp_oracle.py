@@ -3,7 +3,6 @@ through every layer, the decode's closed forms, bfloat16 rounding."""
 import math
 
 import numpy as np
-import pytest
 
 import qsg_workloads as W
 from oracle import mlp
