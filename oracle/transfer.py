@@ -139,3 +139,84 @@ def abs_bound(L: int, k: float, kp: float, jx, jy, x: np.ndarray,
     error of any evaluation order of T x."""
     assert kp >= 0
     return apply(L, k, kp, jx, jy, 1, np.abs(np.asarray(x, dtype=np.float64)), w)
+
+
+# --------------------------------------------------------------------------
+# Ground-state correlations (App. E, the consistency checks of EDQSG): for a
+# sector vector v (the leading eigenvector |GS>), M_xy = <GS| sZ_x sZ_y |GS>,
+# R_xyzu = <GS| sZ_x sZ_y sZ_z sZ_u |GS>, and the L_tau -> infinity values
+#   Q2 = Tr M^2,  F = Tr M Mt,  Q4 = sum_{x,y,z,u} R_xyzu^2,
+# Mt_xy = M_xy [cos(2 pi (x1 - y1)/L) + cos(2 pi (x2 - y2)/L)] / 2.
+# In either sector the weight of the basis pair {n, ~n} is v_n^2 (the
+# operators are even under the global flip), normalised by |v|^2.
+# --------------------------------------------------------------------------
+def ground_correlations(L: int, v: np.ndarray) -> Dict[str, float]:
+    """Q2, Q4, F from the definitions: every ordered pair and quadruple of
+    sites summed over every basis state (small L only)."""
+    V = L * L
+    N = sector_dim(L)
+    assert N <= 1 << 8
+    p = np.asarray(v, dtype=np.float64) ** 2
+    p = p / p.sum()
+    idx = np.arange(N, dtype=np.int64)
+    S = 1 - 2 * ((idx[:, None] >> np.arange(V)[None, :]) & 1)     # last site +1
+    M = np.einsum("n,nx,ny->xy", p, S, S)
+    x1 = np.arange(V) % L
+    x2 = np.arange(V) // L
+    cw = 0.5 * (np.cos(2 * math.pi * (x1[:, None] - x1[None, :]) / L) +
+                np.cos(2 * math.pi * (x2[:, None] - x2[None, :]) / L))
+    Mt = M * cw
+    Q4 = 0.0
+    for x in range(V):
+        for y in range(V):
+            Sxy = p * S[:, x] * S[:, y]
+            R = np.einsum("n,nz,nu->zu", Sxy, S, S)
+            Q4 += float((R ** 2).sum())
+    return {"Q2": float(np.trace(M @ M)), "Q4": Q4, "F": float(np.trace(M @ Mt))}
+
+
+def walsh_hadamard(x: np.ndarray) -> np.ndarray:
+    """sum_n x_n (-1)^popcount(n & m) for every mask m, one XOR-stride round
+    per bit (the unnormalised Walsh-Hadamard transform)."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.size
+    n = N.bit_length() - 1
+    idx = np.arange(N, dtype=np.int64)
+    for j in range(n):
+        sign = 1 - 2 * ((idx >> j) & 1)
+        x = sign * x + x[idx ^ (1 << j)]
+    return x
+
+
+def ground_correlations_wht(L: int, v: np.ndarray) -> Dict[str, float]:
+    """The same three numbers from the Walsh-Hadamard transform W of v^2:
+    for a set S of sites, R_S = W[S without the last site] / W[0] (the last
+    site's spin is +1 in the sector states).  Ordered pairs and quadruples
+    of sites reduce to the set of sites met an odd number of times, which is
+    empty, a pair or a quadruple:
+      Q2 = V + 2 sum_{|S|=2} R_S^2,
+      F  = V + sum_{S={x,y}} R_S^2 [cos(2 pi dx1/L) + cos(2 pi dx2/L)],
+      Q4 = 3V^2 - 2V + (12V - 16) sum_{|S|=2} R_S^2 + 24 sum_{|S|=4} R_S^2."""
+    from itertools import combinations
+    V = L * L
+    W = walsh_hadamard(np.asarray(v, dtype=np.float64) ** 2)
+    W = W / W[0]
+    last = V - 1
+
+    def mask(s):
+        return sum(1 << i for i in s if i != last)
+
+    s2 = sF = 0.0
+    for x, y in combinations(range(V), 2):
+        r2 = W[mask((x, y))] ** 2
+        s2 += r2
+        sF += r2 * (math.cos(2 * math.pi * (x % L - y % L) / L) +
+                    math.cos(2 * math.pi * (x // L - y // L) / L))
+    s4 = sum(W[mask(q)] ** 2 for q in combinations(range(V), 4))
+    return {"Q2": V + 2 * s2, "Q4": 3 * V * V - 2 * V + (12 * V - 16) * s2 + 24 * s4,
+            "F": V + sF}
+
+
+def xi2(Q2: float, F: float, L: int) -> float:
+    """Second-moment correlation length (App. E): sqrt(Q2/F - 1) / (2 sin(pi/L))."""
+    return math.sqrt(Q2 / F - 1.0) / (2.0 * math.sin(math.pi / L))

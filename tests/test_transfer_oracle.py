@@ -140,3 +140,43 @@ def test_leading_eigenpairs_at_L4_are_eigenpairs():
     assert e["values"][0] > o["values"][0] > 0
     v = e["vector"] * np.sign(e["vector"].sum())
     assert np.all(v > 0)
+
+
+def test_walsh_hadamard_is_the_hadamard_matrix():
+    from scipy.linalg import hadamard
+    rng = np.random.default_rng(12)
+    for n in (1, 3, 6):
+        x = rng.standard_normal(1 << n)
+        assert np.allclose(transfer.walsh_hadamard(x), hadamard(1 << n) @ x, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_ground_correlations_transform_equals_definitions(L):
+    """Q2, Q4, F through the Walsh-Hadamard route (the reduction of ordered
+    pairs and quadruples to odd-multiplicity sets) equal the plain sums over
+    every ordered pair and quadruple of sites: random vectors and the
+    leading eigenvector of a sample."""
+    rng = np.random.default_rng(13 + L)
+    case_j = random_j(L, 14 + L)
+    gs = transfer.leading_eigenpairs(L, 0.31, 0.31, *case_j, 1)["vector"]
+    for v in (rng.standard_normal(transfer.sector_dim(L)), gs):
+        a = transfer.ground_correlations(L, v)
+        b = transfer.ground_correlations_wht(L, v)
+        for key in ("Q2", "Q4", "F"):
+            assert abs(a[key] - b[key]) <= 1e-11 * max(abs(a[key]), 1.0), (key, a, b)
+
+
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_ground_correlations_closed_forms(L):
+    """Independent spins (uniform weights): M = 1, R = 0 off the empty set,
+    so Q2 = F = V and Q4 = 3V^2 - 2V; one ordered state: every correlation
+    is 1, Q2 = V^2, Q4 = V^4 and F = 0 (the cosines sum to zero)."""
+    V = L * L
+    N = transfer.sector_dim(L)
+    u = transfer.ground_correlations_wht(L, np.ones(N))
+    assert np.allclose([u["Q2"], u["Q4"], u["F"]], [V, 3 * V * V - 2 * V, V], rtol=1e-12)
+    e = np.zeros(N)
+    e[0] = 1.0
+    o = transfer.ground_correlations_wht(L, e)
+    assert np.allclose([o["Q2"], o["Q4"]], [V * V, V ** 4], rtol=1e-12)
+    assert abs(o["F"]) < 1e-9 * V * V
