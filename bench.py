@@ -367,8 +367,12 @@ def transfer_bench(args):
     except (TypeError, KeyError, ValueError):
         tm_traffic = None
     t0 = time.perf_counter()
-    lz = qsg.tm_lanczos(d, 300, 2, 1e-9, seed=5, stream=s)
+    lz = qsg.tm_lanczos(d, 300, 2, 1e-9, seed=5, want_vector=True, stream=s)
     lanczos_s = time.perf_counter() - t0
+    qsg.tm_correlations(case.L, lz["vector"], stream=s)  # warm-up
+    t0 = time.perf_counter()
+    corr = qsg.tm_correlations(case.L, lz["vector"], stream=s)
+    corr_s = time.perf_counter() - t0
     result = {"metric": "transfer-matrix product time", "value": round(sec * 1e6, 3),
               "unit": "us per product", "higher_is_better": False, "steps": reps,
               "dtype": "f64", "data": "synthetic",
@@ -388,6 +392,10 @@ def transfer_bench(args):
                           "steps": lz["iters"], "seconds": round(lanczos_s, 3),
                           "note": "two largest even eigenvalues, residual <= 1e-9 |lambda|, full "
                                   "reorthogonalisation"},
+              "ground_state_correlations": {k: round(v, 9) for k, v in corr.items()} | {
+                  "seconds": round(corr_s, 5),
+                  "note": "Q2, Q4, F of the leading even eigenvector (L_tau -> infinity), "
+                          "Walsh-Hadamard transform of its squares on the device"},
               "note": "HIP events around back-to-back products on one stream"}
     if not args.no_cpu_baseline:
         from oracle import transfer

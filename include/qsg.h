@@ -329,6 +329,23 @@ qsg_status qsg_tm_lanczos(const qsg_tm_desc* d, uint32_t max_iter, uint32_t n_ei
                           uint64_t seed, void* d_ws, size_t ws_bytes, double* eigs,
                           double* resid, uint32_t* iters, double* d_vec, void* hip_stream);
 
+/* Ground-state correlation functions (paper: App. E, the consistency checks
+ * of EDQSG, L_tau -> infinity): for the sector vector d_vec (qsg_tm_dim(L)
+ * doubles, device; normally the leading eigenvector of the even sector,
+ * any norm: the weights v_n^2 are normalised), with
+ * M_xy = <v| sZ_x sZ_y |v>, R_xyzu = <v| sZ_x sZ_y sZ_z sZ_u |v> and
+ * Mt_xy = M_xy [cos(2 pi (x1-y1)/L) + cos(2 pi (x2-y2)/L)] / 2:
+ *   out[0] = Q2 = Tr M^2,  out[1] = Q4 = sum_{x,y,z,u} R_xyzu^2,
+ *   out[2] = F = Tr M Mt   (host, 3 doubles).
+ * Computed from the Walsh-Hadamard transform of v^2 on the device (the
+ * product's passes with the factor (a, b) -> (a + b, a - b)) and a
+ * fixed-order reduction over the pairs and quadruples of sites.  d_ws:
+ * qsg_tm_correlations_workspace_bytes(L) bytes of device memory, caller
+ * owned.  Synchronises hip_stream. */
+size_t qsg_tm_correlations_workspace_bytes(uint32_t L);
+qsg_status qsg_tm_correlations(uint32_t L, const double* d_vec, void* d_ws, size_t ws_bytes,
+                               double* out, void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Learned Gamma ladder: a 6 -> 128 -> 128 -> 128 -> 32 MLP (exact-erf GELU on
  * the hidden layers) mapping (L, L_tau, beta, frustrated-plaquette fraction,

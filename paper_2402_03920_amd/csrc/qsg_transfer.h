@@ -29,6 +29,15 @@ struct TmParams {
 // one for L <= 3.
 hipError_t launch_tm_apply(const TmParams& P, const double* in, double* out, hipStream_t s);
 
+// out = the Walsh-Hadamard transform of in^2 elementwise over the n index
+// bits: out[m] = sum_k in[k]^2 (-1)^popcount(k & m) (in == out allowed; the
+// same passes as the product with the factor (a, b) -> (a + b, a - b)).
+hipError_t launch_tm_wht_squares(const TmParams& P, const double* in, double* out, hipStream_t s);
+// out[0..2] = sum_e w[3e + i] (W[mask[e]] / W[0])^2 for i = 0, 1, 2 (one
+// block, fixed order).
+hipError_t launch_tm_corr(const double* W, const uint32_t* mask, const double* w, uint32_t n,
+                          double* out, hipStream_t s);
+
 // Lanczos support, float64, deterministic (fixed reduction order).
 constexpr uint32_t kTmDotBlocks = 512;  // partial sums per dot product
 // h[i] = <V[i], w> for i < nv (V: nv vectors of N, contiguous); partial:

@@ -43,8 +43,10 @@ __device__ __forceinline__ void stage_table(const TmParams& P, double* wt) {
     for (uint32_t i = threadIdx.x; i < kTmTable; i += blockDim.x) wt[i] = P.wtab[i];
 }
 
-// The site factors of the bits of a register index: pairs (r, r | 2^q).
-template <int R>
+// The factors of the bits of a register index, pairs (r, r | 2^q): the
+// site factor (a, b) -> (jp a + jm b, jp b + jm a), or with kHad the
+// Walsh-Hadamard factor (a, b) -> (a + b, a - b).
+template <int R, bool kHad = false>
 __device__ __forceinline__ void rounds(double (&x)[R], double jp, double jm) {
 #pragma unroll
     for (int q = 1; q < R; q <<= 1) {
@@ -52,8 +54,13 @@ __device__ __forceinline__ void rounds(double (&x)[R], double jp, double jm) {
         for (int r = 0; r < R; ++r) {
             if (r & q) continue;
             const double a = x[r], b = x[r | q];
-            x[r] = jp * a + jm * b;
-            x[r | q] = jp * b + jm * a;
+            if (kHad) {
+                x[r] = a + b;
+                x[r | q] = a - b;
+            } else {
+                x[r] = jp * a + jm * b;
+                x[r | q] = jp * b + jm * a;
+            }
         }
     }
 }
@@ -63,7 +70,7 @@ __device__ __forceinline__ void rounds(double (&x)[R], double jp, double jm) {
 // so that each thread holds the 16 values of bits 4-7 for one (bits 0-3,
 // bits 8-11), four rounds; with k12 transpose again to bits 8-11, four more
 // rounds.  Stores are coalesced (consecutive threads, consecutive states).
-template <bool k12>
+template <bool k12, bool kHad>
 __device__ __forceinline__ void finish_low_tile(double* lds, double (&x)[16], size_t base,
                                                 uint32_t tt, const TmParams& P, double* out) {
 #pragma unroll
@@ -79,7 +86,7 @@ __device__ __forceinline__ void finish_low_tile(double* lds, double (&x)[16], si
         const uint32_t e = lo + 16 * (uint32_t)s + 256 * cc;
         y[s] = lds[e + (e >> 4)];
     }
-    rounds<16>(y, P.jp, P.jm);
+    rounds<16, kHad>(y, P.jp, P.jm);
     if (!k12) {
 #pragma unroll
         for (int s = 0; s < 16; ++s) out[base + lo + 16 * (uint32_t)s + 256 * cc] = y[s];
@@ -97,17 +104,18 @@ __device__ __forceinline__ void finish_low_tile(double* lds, double (&x)[16], si
         const uint32_t e = threadIdx.x + 256 * (uint32_t)q;
         y[q] = lds[e + (e >> 4)];
     }
-    rounds<16>(y, P.jp, P.jm);
+    rounds<16, kHad>(y, P.jp, P.jm);
 #pragma unroll
     for (int q = 0; q < 16; ++q) out[base + threadIdx.x + 256 * (uint32_t)q] = y[q];
 }
 
 // First pass (n >= 15): block b takes tile b and its mirror (indices
 // N-1-i), applies W, the last site's round between mirrored elements and
-// the rounds of bits 0-7 (k12: 0-11) of both tiles.  in == out is allowed:
-// every element is read before any is written, and blocks touch disjoint
-// tiles.
-template <bool k12>
+// the rounds of bits 0-7 (k12: 0-11) of both tiles.  With kHad it squares
+// the input and applies the Walsh-Hadamard factors of the same bits only.
+// in == out is allowed: every element is read before any is written, and
+// blocks touch disjoint tiles.
+template <bool k12, bool kHad>
 __global__ void __launch_bounds__(kTmThreads)
 k_tm_first(const TmParams P, const double* in, double* out) {
     __shared__ double lds[kTile + kTile / 16];
@@ -133,22 +141,30 @@ k_tm_first(const TmParams P, const double* in, double* out) {
         xb[r + 1] = vb.y;
     }
     __syncthreads();  // table staged
+    if (kHad) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        xa[r] *= wt[unsat(P, (uint32_t)(base_a + ea) + (uint32_t)r)];
-        xb[r] *= wt[unsat(P, (uint32_t)(base_b + eb) + (uint32_t)r)];
-    }
+        for (int r = 0; r < 16; ++r) {
+            xa[r] *= xa[r];
+            xb[r] *= xb[r];
+        }
+    } else {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const double a = xa[r], b = xb[15 - r];
-        xa[r] = P.jp * a + P.jm_last * b;
-        xb[15 - r] = P.jp * b + P.jm_last * a;
+        for (int r = 0; r < 16; ++r) {
+            xa[r] *= wt[unsat(P, (uint32_t)(base_a + ea) + (uint32_t)r)];
+            xb[r] *= wt[unsat(P, (uint32_t)(base_b + eb) + (uint32_t)r)];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const double a = xa[r], b = xb[15 - r];
+            xa[r] = P.jp * a + P.jm_last * b;
+            xb[15 - r] = P.jp * b + P.jm_last * a;
+        }
     }
-    rounds<16>(xa, P.jp, P.jm);
-    rounds<16>(xb, P.jp, P.jm);
-    finish_low_tile<k12>(lds, xa, base_a, t, P, out);
+    rounds<16, kHad>(xa, P.jp, P.jm);
+    rounds<16, kHad>(xb, P.jp, P.jm);
+    finish_low_tile<k12, kHad>(lds, xa, base_a, t, P, out);
     __syncthreads();  // LDS reused for the mirror tile
-    finish_low_tile<k12>(lds, xb, base_b, 255 - t, P, out);
+    finish_low_tile<k12, kHad>(lds, xb, base_b, 255 - t, P, out);
 }
 
 // Second pass of L = 5 (n = 24): bits 12-23 of the 32768 states
@@ -169,6 +185,7 @@ __device__ __forceinline__ uint32_t hi_row_b(uint32_t h) {  // bit 9 = half: rem
     return (h & 511u) | ((h >> 10) << 9);
 }
 
+template <bool kHad>
 __global__ void __launch_bounds__(kHiThreads)
 k_tm_hi12(const TmParams P, double* __restrict__ out) {
     __shared__ double lds[2048 * kHiCols];
@@ -188,7 +205,7 @@ k_tm_hi12(const TmParams P, double* __restrict__ out) {
     const uint32_t hb = t >> 3;
 #pragma unroll
     for (int r = 0; r < 32; ++r) x[r] = out[base + ((size_t)((uint32_t)r + 32 * hb) << 12) + c];
-    rounds<32>(x, P.jp, P.jm);
+    rounds<32, kHad>(x, P.jp, P.jm);
     // layout 2: h = hl + 32 s + 1024 hh, hl = bits 0-4, hh = bits 10-11
     const uint32_t hl = (t >> 3) & 31u, hh = t >> 8;
     const uint32_t half = t >> 9;  // h bit 11 in layouts 1 and 2
@@ -207,7 +224,7 @@ k_tm_hi12(const TmParams P, double* __restrict__ out) {
                 x[s] = lds[hi_row_a(hl + 32 * (uint32_t)s + 1024 * hh) * kHiCols + c];
         }
     }
-    rounds<32>(x, P.jp, P.jm);
+    rounds<32, kHad>(x, P.jp, P.jm);
     // layout 3: h = hm + 128 g + 1024 q, register 4 g + q, hm = bits 0-6
     const uint32_t hm = t >> 3;
 #pragma unroll
@@ -229,15 +246,15 @@ k_tm_hi12(const TmParams P, double* __restrict__ out) {
         for (int r = 0; r < 32; ++r) {
             if (r & q) continue;
             const double a = x[r], b = x[r | q];
-            x[r] = P.jp * a + P.jm * b;
-            x[r | q] = P.jp * b + P.jm * a;
+            x[r] = kHad ? a + b : P.jp * a + P.jm * b;
+            x[r | q] = kHad ? a - b : P.jp * b + P.jm * a;
         }
     }
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
         const uint32_t g = (uint32_t)(j >> 2), q = (uint32_t)(j & 3);
         const size_t i = base + ((size_t)(hm + 128 * g + 1024 * q) << 12) + c;
-        out[i] = x[j] * wt[unsat(P, (uint32_t)i)];
+        out[i] = kHad ? x[j] : x[j] * wt[unsat(P, (uint32_t)i)];
     }
 }
 
@@ -245,7 +262,7 @@ k_tm_hi12(const TmParams P, double* __restrict__ out) {
 // base + h 2^b0 + c, h < 2^(4+MB), c < C consecutive (C = 4096 / 2^(4+MB));
 // the block index fills the bits between log2 C and b0 and above the pass.
 // The last pass also applies W.
-template <int MB, bool kLast>
+template <int MB, bool kLast, bool kHad>
 __global__ void __launch_bounds__(kTmThreads)
 k_tm_pass(const TmParams P, uint32_t b0, double* __restrict__ out) {
     constexpr int M = 4 + MB;
@@ -256,7 +273,7 @@ k_tm_pass(const TmParams P, uint32_t b0, double* __restrict__ out) {
     constexpr int CP = C + 1;     // padded LDS row
     __shared__ double lds[(1 << M) * CP];
     __shared__ double wt[kTmTable];
-    if (kLast) stage_table(P, wt);
+    if (kLast && !kHad) stage_table(P, wt);
     const uint32_t nlow = b0 - LOGC;
     const size_t B = blockIdx.x;
     const size_t base = ((B & ((1u << nlow) - 1)) << LOGC) | ((B >> nlow) << (b0 + M));
@@ -266,7 +283,7 @@ k_tm_pass(const TmParams P, uint32_t b0, double* __restrict__ out) {
     double x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = out[base + ((uint32_t)r + 16 * hh) * stride + c];
-    rounds<16>(x, P.jp, P.jm);
+    rounds<16, kHad>(x, P.jp, P.jm);
 #pragma unroll
     for (int r = 0; r < 16; ++r) lds[((uint32_t)r + 16 * hh) * CP + c] = x[r];
     __syncthreads();
@@ -277,19 +294,21 @@ k_tm_pass(const TmParams P, uint32_t b0, double* __restrict__ out) {
         double y[HB];
 #pragma unroll
         for (int s = 0; s < HB; ++s) y[s] = lds[(lo + 16 * (uint32_t)s) * CP + cc];
-        rounds<HB>(y, P.jp, P.jm);
+        rounds<HB, kHad>(y, P.jp, P.jm);
 #pragma unroll
         for (int s = 0; s < HB; ++s) {
             const size_t i = base + (lo + 16 * (uint32_t)s) * stride + cc;
             double v = y[s];
-            if (kLast) v *= wt[unsat(P, (uint32_t)i)];
+            if (kLast && !kHad) v *= wt[unsat(P, (uint32_t)i)];
             out[i] = v;
         }
     }
 }
 
 // n <= 8: one block, one element per thread, every round through LDS in the
-// paper's order (W, bits 0 .. n-1, the last site, W).
+// paper's order (W, bits 0 .. n-1, the last site, W); with kHad the squared
+// input and the Walsh-Hadamard factors of bits 0 .. n-1 only.
+template <bool kHad>
 __global__ void __launch_bounds__(kTmThreads)
 k_tm_small(const TmParams P, const double* in, double* out) {
     __shared__ double v[kTmThreads];
@@ -298,12 +317,20 @@ k_tm_small(const TmParams P, const double* in, double* out) {
     __syncthreads();
     const uint32_t N = 1u << P.n, t = threadIdx.x;
     const bool live = t < N;
-    double x = live ? in[t] * wt[unsat(P, t)] : 0.0;
+    double x = 0.0;
+    if (live) x = kHad ? in[t] * in[t] : in[t] * wt[unsat(P, t)];
     for (uint32_t j = 0; j < P.n; ++j) {
         if (live) v[t] = x;
         __syncthreads();
-        if (live) x = P.jp * x + P.jm * v[t ^ (1u << j)];
+        if (live) {
+            const double o = v[t ^ (1u << j)];
+            x = kHad ? ((t >> j) & 1u ? o - x : x + o) : P.jp * x + P.jm * o;
+        }
         __syncthreads();
+    }
+    if (kHad) {
+        if (live) out[t] = x;
+        return;
     }
     if (live) v[t] = x;
     __syncthreads();
@@ -398,25 +425,71 @@ uint32_t stream_blocks(size_t N) {
     return (uint32_t)(b < 4096 ? b : 4096);
 }
 
-}  // namespace
-
-hipError_t launch_tm_apply(const TmParams& P, const double* in, double* out, hipStream_t s) {
+template <bool kHad>
+hipError_t launch_passes(const TmParams& P, const double* in, double* out, hipStream_t s) {
     if (P.n <= 8) {
-        hipLaunchKernelGGL(k_tm_small, dim3(1), dim3(kTmThreads), 0, s, P, in, out);
+        hipLaunchKernelGGL(k_tm_small<kHad>, dim3(1), dim3(kTmThreads), 0, s, P, in, out);
         return hipGetLastError();
     }
     const size_t N = (size_t)1 << P.n;
     if (P.n == 15) {  // bits 0-7, then 8-14
-        hipLaunchKernelGGL(k_tm_first<false>, dim3((uint32_t)(N / (2 * kTile))), dim3(kTmThreads), 0,
-                           s, P, in, out);
-        hipLaunchKernelGGL((k_tm_pass<3, true>), dim3((uint32_t)(N / kTile)), dim3(kTmThreads), 0, s,
-                           P, 8u, out);
+        hipLaunchKernelGGL((k_tm_first<false, kHad>), dim3((uint32_t)(N / (2 * kTile))),
+                           dim3(kTmThreads), 0, s, P, in, out);
+        hipLaunchKernelGGL((k_tm_pass<3, true, kHad>), dim3((uint32_t)(N / kTile)), dim3(kTmThreads),
+                           0, s, P, 8u, out);
     } else {          // n == 24: bits 0-11, then 12-23
-        hipLaunchKernelGGL(k_tm_first<true>, dim3((uint32_t)(N / (2 * kTile))), dim3(kTmThreads), 0,
-                           s, P, in, out);
-        hipLaunchKernelGGL(k_tm_hi12, dim3((uint32_t)(N / (4096 * kHiCols))), dim3(kHiThreads), 0, s,
-                           P, out);
+        hipLaunchKernelGGL((k_tm_first<true, kHad>), dim3((uint32_t)(N / (2 * kTile))),
+                           dim3(kTmThreads), 0, s, P, in, out);
+        hipLaunchKernelGGL(k_tm_hi12<kHad>, dim3((uint32_t)(N / (4096 * kHiCols))), dim3(kHiThreads),
+                           0, s, P, out);
     }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tm_apply(const TmParams& P, const double* in, double* out, hipStream_t s) {
+    return launch_passes<false>(P, in, out, s);
+}
+
+hipError_t launch_tm_wht_squares(const TmParams& P, const double* in, double* out, hipStream_t s) {
+    return launch_passes<true>(P, in, out, s);
+}
+
+namespace {
+
+// Q2, Q4 and F sums from the transform: entry e adds wq2[e], wq4[e], wf[e]
+// times (W[mask[e]] / W[0])^2; one block, fixed order.
+__global__ void __launch_bounds__(kTmThreads)
+k_tm_corr(const double* __restrict__ W, const uint32_t* __restrict__ mask,
+          const double* __restrict__ wts, uint32_t n, double* __restrict__ out) {
+    __shared__ double red[kTmThreads / 64];
+    const double inv = 1.0 / W[0];
+    double a2 = 0.0, a4 = 0.0, af = 0.0;
+    for (uint32_t e = threadIdx.x; e < n; e += kTmThreads) {
+        const double r = W[mask[e]] * inv;
+        const double r2 = r * r;
+        a2 += wts[3 * e] * r2;
+        a4 += wts[3 * e + 1] * r2;
+        af += wts[3 * e + 2] * r2;
+    }
+    const double s2 = block_sum(a2, red);
+    __syncthreads();
+    const double s4 = block_sum(a4, red);
+    __syncthreads();
+    const double sf = block_sum(af, red);
+    if (threadIdx.x == 0) {
+        out[0] = s2;
+        out[1] = s4;
+        out[2] = sf;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_tm_corr(const double* W, const uint32_t* mask, const double* wts, uint32_t n,
+                          double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_tm_corr, dim3(1), dim3(kTmThreads), 0, s, W, mask, wts, n, out);
     return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <initializer_list>
 #include <cstring>
 #include <limits>
 #include <vector>
@@ -146,6 +147,58 @@ std::vector<double> tri_vector(const std::vector<double>& a, const std::vector<d
     return z;
 }
 
+// Entries of the Walsh-Hadamard transform of v^2 that the ground-state
+// correlations need (App. E): a set S of sites has R_S = W[S without the
+// last site] / W[0].  Ordered pairs and quadruples of sites reduce to the
+// set met an odd number of times (empty, a pair, a quadruple), so
+//   Q2 = V + 2 sum_pairs R^2,
+//   Q4 = 3V^2 - 2V + (12V - 16) sum_pairs R^2 + 24 sum_quadruples R^2,
+//   F  = V + sum_pairs R^2 [cos(2 pi dx1 / L) + cos(2 pi dx2 / L)].
+// Weights per entry: (Q2, Q4, F).
+struct CorrTable {
+    std::vector<uint32_t> mask;
+    std::vector<double> w;
+    double q2 = 0, q4 = 0, f = 0;  // the empty set's terms
+};
+
+CorrTable corr_table(uint32_t L) {
+    CorrTable t;
+    const uint32_t V = L * L, last = V - 1;
+    auto bits = [&](std::initializer_list<uint32_t> s) {
+        uint32_t m = 0;
+        for (uint32_t i : s)
+            if (i != last) m |= 1u << i;
+        return m;
+    };
+    const double two_pi = 6.283185307179586476925286766559;
+    for (uint32_t x = 0; x < V; ++x)
+        for (uint32_t y = x + 1; y < V; ++y) {
+            t.mask.push_back(bits({x, y}));
+            const double dx1 = (double)(x % L) - (double)(y % L);
+            const double dx2 = (double)(x / L) - (double)(y / L);
+            t.w.insert(t.w.end(), {2.0, 12.0 * V - 16.0,
+                                   std::cos(two_pi * dx1 / L) + std::cos(two_pi * dx2 / L)});
+        }
+    for (uint32_t a = 0; a < V; ++a)
+        for (uint32_t b = a + 1; b < V; ++b)
+            for (uint32_t c = b + 1; c < V; ++c)
+                for (uint32_t d = c + 1; d < V; ++d) {
+                    t.mask.push_back(bits({a, b, c, d}));
+                    t.w.insert(t.w.end(), {0.0, 24.0, 0.0});
+                }
+    t.q2 = V;
+    t.q4 = 3.0 * V * V - 2.0 * V;
+    t.f = V;
+    return t;
+}
+
+size_t corr_entries(uint32_t L) {
+    const size_t V = (size_t)L * L;
+    return V * (V - 1) / 2 + V * (V - 1) * (V - 2) * (V - 3) / 24;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 }  // namespace
 
 extern "C" {
@@ -256,6 +309,51 @@ qsg_status qsg_tm_lanczos(const qsg_tm_desc* d, uint32_t max_iter, uint32_t n_ei
         TM_HIP(qsg::launch_tm_combine(V, m, N, y, d_vec, s));
         TM_HIP(hipStreamSynchronize(s));
     }
+    return QSG_OK;
+}
+
+size_t qsg_tm_correlations_workspace_bytes(uint32_t L) {
+    const uint64_t N = qsg_tm_dim(L);
+    if (!N) return 0;
+    const size_t E = corr_entries(L);
+    return align256(N * sizeof(double)) + align256(E * sizeof(uint32_t)) +
+           align256(3 * E * sizeof(double)) + align256(4 * sizeof(double));
+}
+
+qsg_status qsg_tm_correlations(uint32_t L, const double* d_vec, void* d_ws, size_t ws_bytes,
+                               double* out, void* hip_stream) {
+    if (L > QSG_TM_MAX_L)
+        return qsg::report_error(QSG_E_UNSUPPORTED, "L = %u > %u", L, QSG_TM_MAX_L);
+    if (L < 2) return qsg::report_error(QSG_E_INVALID, "L = %u < 2", L);
+    if (!d_vec || !d_ws || !out) return qsg::report_error(QSG_E_INVALID, "null buffer");
+    if (ws_bytes < qsg_tm_correlations_workspace_bytes(L))
+        return qsg::report_error(QSG_E_BUFFER, "workspace needs %zu bytes",
+                                 qsg_tm_correlations_workspace_bytes(L));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t N = (size_t)qsg_tm_dim(L);
+    const CorrTable t = corr_table(L);
+    const uint32_t E = (uint32_t)t.mask.size();
+    char* base = static_cast<char*>(d_ws);
+    double* W = reinterpret_cast<double*>(base);
+    uint32_t* mask = reinterpret_cast<uint32_t*>(base + align256(N * sizeof(double)));
+    double* w = reinterpret_cast<double*>(reinterpret_cast<char*>(mask) +
+                                          align256(E * sizeof(uint32_t)));
+    double* sums = reinterpret_cast<double*>(reinterpret_cast<char*>(w) +
+                                             align256(3 * (size_t)E * sizeof(double)));
+    TmParams P;
+    std::memset(&P, 0, sizeof P);
+    P.L = L;
+    P.n = L * L - 1;
+    TM_HIP(qsg::launch_tm_wht_squares(P, d_vec, W, s));
+    TM_HIP(hipMemcpyAsync(mask, t.mask.data(), E * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    TM_HIP(hipMemcpyAsync(w, t.w.data(), 3 * (size_t)E * sizeof(double), hipMemcpyHostToDevice, s));
+    TM_HIP(qsg::launch_tm_corr(W, mask, w, E, sums, s));
+    double h[3];
+    TM_HIP(hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+    out[0] = t.q2 + h[0];
+    out[1] = t.q4 + h[1];
+    out[2] = t.f + h[2];
     return QSG_OK;
 }
 

@@ -118,6 +118,9 @@ _SIGS = {
     "qsg_tm_lanczos": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_double, C.c_uint64,
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_void_p]),
+    "qsg_tm_correlations_workspace_bytes": (C.c_size_t, [C.c_uint32]),
+    "qsg_tm_correlations": (C.c_int32, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                        C.c_void_p, C.c_void_p]),
     "qsg_mlp_param_count": (C.c_uint32, []),
     "qsg_mlp_workspace_floats": (C.c_size_t, [C.c_uint32]),
     "qsg_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
@@ -518,6 +521,26 @@ def tm_lanczos(desc: qsg_tm_desc, max_iter: int, n_eig: int = 2, tol: float = 1e
                                 C.c_void_p(ws.data_ptr()), nbytes, _ptr(eigs), _ptr(resid),
                                 _ptr(iters), _dp(vec), sp))
     return {"values": eigs, "resid": resid, "iters": int(iters[0]), "vector": vec}
+
+
+def tm_correlations(L: int, vec, stream=None) -> dict:
+    """Ground-state correlations Q2, Q4, F of a sector vector (a float64
+    device tensor of tm_dim(L) entries; qsg_tm_correlations) and the
+    second-moment correlation length sqrt(Q2/F - 1) / (2 sin(pi/L))."""
+    import math
+    import torch
+    n = tm_dim(L)
+    if vec.dtype != torch.float64 or not vec.is_cuda or vec.numel() != n or not vec.is_contiguous():
+        raise ValueError(f"need a contiguous float64 device tensor of {n} entries")
+    nbytes = int(lib().qsg_tm_correlations_workspace_bytes(L))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=vec.device)
+    out = np.zeros(3)
+    sp = C.c_void_p(stream.cuda_stream) if stream is not None else _stream_ptr()
+    _check(lib().qsg_tm_correlations(L, C.c_void_p(vec.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                     nbytes, _ptr(out), sp))
+    q2, q4, f = (float(v) for v in out)
+    xi = math.sqrt(q2 / f - 1.0) / (2.0 * math.sin(math.pi / L)) if f > 0 and q2 > f else float("nan")
+    return {"Q2": q2, "Q4": q4, "F": f, "xi2": xi}
 
 
 def _torch_f64():

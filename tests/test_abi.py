@@ -189,3 +189,21 @@ def test_transfer_matrix_sizes_and_validation_without_the_device():
         rc = lib.qsg_tm_lanczos(C.byref(d), max_iter, n_eig, 1e-10, 1, dummy, ws, out.ctypes.data,
                                 out.ctypes.data, it.ctypes.data, None, None)
         assert rc in (qsg.QSG_E_INVALID, qsg.QSG_E_BUFFER), (max_iter, n_eig, ws, rc)
+
+
+def test_correlations_sizes_and_validation_without_the_device():
+    from paper_2402_03920_amd import qsg
+    lib = qsg.lib()
+    assert lib.qsg_tm_correlations_workspace_bytes(1) == 0
+    assert lib.qsg_tm_correlations_workspace_bytes(6) == 0
+    assert lib.qsg_tm_correlations_workspace_bytes(5) >= (1 << 24) * 8 + 12950 * 28
+    out = np.zeros(3)
+    dummy = C.c_void_p(1)  # never dereferenced: every case fails validation first
+    big = lib.qsg_tm_correlations_workspace_bytes(3)
+    for L, vec, ws, nbytes, want in ((1, dummy, dummy, big, qsg.QSG_E_INVALID),
+                                     (6, dummy, dummy, big, qsg.QSG_E_UNSUPPORTED),
+                                     (3, None, dummy, big, qsg.QSG_E_INVALID),
+                                     (3, dummy, None, big, qsg.QSG_E_INVALID),
+                                     (3, dummy, dummy, 16, qsg.QSG_E_BUFFER)):
+        rc = lib.qsg_tm_correlations(L, vec, ws, nbytes, out.ctypes.data, None)
+        assert rc == want, (L, rc)

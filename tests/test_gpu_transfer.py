@@ -172,3 +172,51 @@ def test_lanczos_full_size_L5():
     e = lanczos_check(case, 1, 2, 300, 1e-9, w=w)
     o = lanczos_check(case, -1, 1, 300, 1e-9, w=w)
     assert e["values"][0] > o["values"][0] > 0
+
+
+def device_correlations(L, v):
+    return qsg.tm_correlations(L, torch.from_numpy(np.ascontiguousarray(v)).cuda())
+
+
+def check_correlations(L, v, want):
+    got = device_correlations(L, v)
+    for key in ("Q2", "Q4", "F"):
+        assert abs(got[key] - want[key]) <= 1e-10 * max(abs(want[key]), 1.0), (L, key, got, want)
+    return got
+
+
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_correlations_match_oracle(L):
+    """Q2, Q4, F (App. E) of random vectors and of the leading even
+    eigenvector: against the plain definitions for L <= 3 and the oracle's
+    own transform route at L = 4; closed forms for uniform and one-state
+    vectors."""
+    say(f"[tm correlations] L={L}")
+    rng = np.random.default_rng(30 + L)
+    case = W.transfer_case(L, 0.31, 0.31, seed=31 + L)
+    gs = transfer.leading_eigenpairs(L, case.k, case.k_perp, case.jx, case.jy, 1)["vector"]
+    ref = transfer.ground_correlations if L <= 3 else transfer.ground_correlations_wht
+    for v in (rng.standard_normal(transfer.sector_dim(L)), gs):
+        check_correlations(L, v, ref(L, v))
+    V = L * L
+    N = transfer.sector_dim(L)
+    check_correlations(L, np.ones(N), {"Q2": V, "Q4": 3 * V * V - 2 * V, "F": V})
+    e = np.zeros(N)
+    e[0] = 2.0  # any norm
+    got = device_correlations(L, e)
+    assert abs(got["Q2"] - V * V) < 1e-9 * V * V and abs(got["Q4"] - V ** 4) < 1e-9 * V ** 4
+    assert abs(got["F"]) < 1e-9 * V * V
+
+
+def test_correlations_of_the_L5_ground_state():
+    """L = 5: the Lanczos ground state's correlations against the oracle's
+    transform route on the same vector (copied from the device)."""
+    case = W.transfer_case()
+    d = qsg.tm_desc(case.L, case.k, case.k_perp, case.jx, case.jy, 1)
+    r = qsg.tm_lanczos(d, 300, 1, 1e-9, seed=5, want_vector=True)
+    v = r["vector"].cpu().numpy()
+    say(f"[tm correlations] L=5 ground state from {r['iters']} Lanczos steps")
+    want = transfer.ground_correlations_wht(5, v)
+    got = check_correlations(5, v, want)
+    say(f"  Q2 {got['Q2']:.6f} Q4 {got['Q4']:.4f} F {got['F']:.6f} xi2 {got['xi2']:.4f}")
+    assert got["Q2"] > got["F"] > 0
