@@ -220,3 +220,45 @@ def test_correlations_of_the_L5_ground_state():
     got = check_correlations(5, v, want)
     say(f"  Q2 {got['Q2']:.6f} Q4 {got['Q4']:.4f} F {got['F']:.6f} xi2 {got['xi2']:.4f}")
     assert got["Q2"] > got["F"] > 0
+
+
+def test_monte_carlo_slices_follow_the_transfer_matrix_ground_state():
+    """The consistency check of MCQSG against EDQSG (App. E): in a long
+    periodic prism a slice is distributed as psi(S)^2, psi the leading
+    eigenvector of the symmetric transfer matrix, so the Monte Carlo mean of
+    the space bond sum per slice equals sum_n v_n^2 Bsp(n) over the even
+    sector (corrections ~ (lambda_odd / lambda_even)^L_tau, negligible at
+    L_tau = 64).  Chain on the device (paper's equal-coupling form, k = 0.31
+    on two equal slots, 64 replicas each), transfer matrix and Lanczos on the
+    device; the comparison is statistical: within 5 standard errors of batch
+    means, while a coupling 0.02 away is many errors off."""
+    L, L_tau, k = 4, 64, 0.31
+    g = W.Group(L, L_tau, 1.0, np.array([k, k]), 90, W.MC_SEED, [77] * 64, ladder="k")
+    with qsg.Ensemble([g], pt_every=10, swaplog_cap=8) as ens:
+        ens.init_spins()
+        ens.sweep(2000, qsg.QSG_BATCHED | qsg.QSG_GRAPH)
+        jx_w, jy_w = ens.get_couplings(0)
+        prev = ens.sums()[0][:, :64].sum()
+        batch_means = []
+        for _ in range(10):
+            ens.sweep(5000, qsg.QSG_BATCHED | qsg.QSG_GRAPH)
+            cur = ens.sums()[0][:, :64].sum()
+            # 500 PT steps x 2 slots x 64 lanes, per slice
+            batch_means.append((cur - prev) / (500 * 2 * 64) / L_tau)
+            prev = cur
+    mc = float(np.mean(batch_means))
+    err = float(np.std(batch_means, ddof=1) / np.sqrt(len(batch_means)))
+    jx = 1 - 2 * (jx_w.astype(np.int64) & 1)
+    jy = 1 - 2 * (jy_w.astype(np.int64) & 1)
+
+    def exact(kk):
+        d = qsg.tm_desc(L, kk, kk, jx, jy, 1)
+        v = qsg.tm_lanczos(d, 300, 1, 1e-12, seed=2, want_vector=True)["vector"].cpu().numpy()
+        p = v * v / np.dot(v, v)
+        B = transfer.slice_bond_sum(np.arange(v.size), L, jx, jy)
+        return float(np.dot(p, B))
+
+    want = exact(k)
+    say(f"[mc vs transfer] <Bsp>/slice MC {mc:.5f} +- {err:.5f}, ground state {want:.5f}")
+    assert abs(mc - want) < 5 * err + 1e-3
+    assert abs(exact(k + 0.02) - mc) > 10 * err
