@@ -9,9 +9,10 @@ def oracle_groups(groups, log_cap):
     return [chain.OracleGroup.from_workload_group(g, log_cap=log_cap) for g in groups]
 
 
-def compare_state(ens, ogs, check_sums=True):
+def compare_state(ens, ogs, check_sums=True, groups=None):
     """Assert that the GPU ensemble and the oracle groups hold identical
-    states.  Returns the number of words compared."""
+    states; oracle group i is the ensemble's group groups[i] (default i).
+    Returns the number of words compared."""
     words = 0
     energies = ens.energies()
     walkers = ens.walkers()
@@ -21,7 +22,8 @@ def compare_state(ens, ogs, check_sums=True):
     sums = ens.sums() if check_sums else None
     hists = ens.histograms() if check_sums else None
     t, p = ens.counters()
-    for i, og in enumerate(ogs):
+    for j, og in enumerate(ogs):
+        i = groups[j] if groups is not None else j
         assert (t, p) == (og.t, og.p), (i, t, p, og.t, og.p)
         sp = ens.get_spins(i)
         if not np.array_equal(sp, og.spins):

@@ -242,6 +242,41 @@ def test_plain_large_shape_truncated_bit_exact():
         compare_state(ens, ogs)
 
 
+def test_plain_large_full_ensemble_sampled_groups():
+    """The bench's configuration: all 64 samples of the L=16, L_tau=128,
+    32-Gamma workload in one batched graph launch per pass with the tuned
+    colour-pass schedule, 20 sweeps with PT every 10; the first and last
+    samples compared with the oracle (all of their state)."""
+    wl = W.plain_large()
+    pick = [0, len(wl.groups) - 1]
+    ogs = oracle_groups([wl.groups[i] for i in pick], 16)
+    say("[parity] c2 full ensemble, oracle for samples", pick)
+    for og in ogs:
+        og.run(20, 10, threads=16)
+    with qsg.Ensemble(wl.groups, pt_every=10, swaplog_cap=16) as ens:
+        for gi in range(len(wl.groups)):
+            ens.set_schedule(gi, 4)
+        ens.init_spins()
+        ens.sweep(20, qsg.QSG_BATCHED | qsg.QSG_GRAPH)
+        compare_state(ens, ogs, groups=pick)
+
+
+def test_uneven_full_ensemble_sampled_groups():
+    """All 256 uneven samples in one batched launch per pass, 20 sweeps with
+    PT every 10; three of the smaller samples compared with the oracle."""
+    wl = W.uneven_ensemble(n_samples=256)
+    pick = [i for i, g in enumerate(wl.groups)
+            if g.L * g.L * g.L_tau * g.n_gamma <= 8 * 8 * 128 * 48][:3]
+    ogs = oracle_groups([wl.groups[i] for i in pick], 16)
+    say("[parity] c3 full ensemble, oracle for samples", pick)
+    for og in ogs:
+        og.run(20, 10, threads=16)
+    with qsg.Ensemble(wl.groups, pt_every=10, swaplog_cap=16) as ens:
+        ens.init_spins()
+        ens.sweep(20, qsg.QSG_BATCHED | qsg.QSG_GRAPH)
+        compare_state(ens, ogs, groups=pick)
+
+
 def test_uneven_groups_truncated_bit_exact():
     """The first uneven-ensemble groups (mixed L, L_tau, N_Gamma) batched in
     one launch per pass, 20 sweeps with PT every 10."""
