@@ -269,6 +269,12 @@ def main():
     if traffic is not None:
         result["roofline"]["hbm_GBps_measured"] = round(traffic / pass_s / 1e9, 2)
         result["roofline"]["hbm_frac_measured"] = round(traffic / pass_s / 8e12, 4)
+        rec = traffic_record(TRAFFIC_FILE, KERNEL_SOURCES)
+        try:  # every VALU instruction the kernel issues (counters), not only the required ones
+            executed = float(rec["valu_instr_per_wave"]) * float(rec["waves_per_launch"]) * 64
+            result["roofline"]["executed_valu_frac"] = round(executed / pass_s / 1e12 / PEAK_VALU_TOPS, 4)
+        except (TypeError, KeyError, ValueError):
+            pass
     result["philox_ceiling"] = dict(ceiling, sweep_required_blocks_per_s=required_rate,
                                     sweep_frac_of_ceiling=round(required_rate / ceiling["blocks_per_s"], 4))
     result["physics"] = physics
