@@ -120,7 +120,11 @@ typedef struct {
 #define QSG_GRAPH 2u    /* with QSG_BATCHED: replay a captured HIP graph       */
 #define QSG_NO_PT 4u    /* skip the PT steps that fall due                     */
 #define QSG_FUSED 8u    /* with QSG_BATCHED: the sweeps of a whole PT chunk in
-                           one launch, one block per slot (small slots from LDS) */
+                           one launch, one block per slot (small slots from LDS);
+                           pays off only when every slot is small (one block
+                           then replaces a launch per colour pass); a slot of
+                           many blocks' worth of words runs serially in its one
+                           block, far slower than the per-pass form          */
 
 /* qsg_measure selectors (one at a time) */
 #define QSG_M_ENERGY 1u    /* int32 [G][N][64][2]: (Bsp, Bt) recomputed now      */
