@@ -27,6 +27,8 @@ extern "C" int qsg_tables_build_host_k(uint32_t N, const double* k, uint32_t cap
                                        uint8_t* eq, uint32_t* len, uint32_t* sw, char* err,
                                        size_t errlen);
 
+static_assert(qsg::kMaxSlots == QSG_MAX_GAMMA, "kernels size per-group arrays by the slot limit");
+
 namespace {
 
 using qsg::GroupDev;

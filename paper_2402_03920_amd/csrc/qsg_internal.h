@@ -135,6 +135,7 @@ __host__ __device__ inline uint32_t sweep_blocks_per_slot(uint32_t V);
 __host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V, uint32_t words);
 __host__ __device__ inline uint32_t swap_blocks(uint32_t V);
 
+constexpr uint32_t kMaxSlots = 64;  // slots per group (the C ABI's QSG_MAX_GAMMA)
 constexpr int kSweepBlock = 256;   // threads per block of a colour pass
 constexpr uint32_t kWaveSize = 64;
 constexpr int kEnergyWords = 64;   // words per thread, batched energy pass

@@ -704,6 +704,13 @@ k_energy_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict
 // currently sits at slot g (it may have arrived from g-1 in this step).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
+    // The pass's energies and the walker labels of this group, lane j's
+    // column of each: the pairs are visited in order, each seeing the state
+    // the previous one left, so the chain runs on LDS instead of on global
+    // loads.  One wave per group: no barriers needed.
+    __shared__ int32_t s_sp[kMaxSlots][64], s_t[kMaxSlots][64];
+    __shared__ uint32_t s_w[kMaxSlots][64];
+    __shared__ uint64_t s_mask[kMaxSlots];
     const uint32_t j = threadIdx.x;
     const uint32_t N = G.N;
     if (N < 2) return;  // nothing to exchange
@@ -714,8 +721,9 @@ __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
         const int32_t bt = V - 2 * c[64 + j];
         c[j] = 0;
         c[64 + j] = 0;
-        G.E[(g * 64 + j) * 2 + 0] = bsp;
-        G.E[(g * 64 + j) * 2 + 1] = bt;
+        s_sp[g][j] = bsp;
+        s_t[g][j] = bt;
+        s_w[g][j] = G.walker[g * 64 + j];
         int64_t* sm = G.sums + (size_t)g * kSumStride;
         sm[j] += bsp;
         sm[64 + j] += bt;
@@ -728,20 +736,24 @@ __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
             sm[160 + j] += q * q;
         }
     }
-    int32_t cur_sp = G.E[j * 2 + 0], cur_t = G.E[j * 2 + 1];
-    uint32_t cur_w = G.walker[j];
+    int32_t cur_sp = s_sp[0][j], cur_t = s_t[0][j];
+    uint32_t cur_w = s_w[0][j];
+    // per-pair table lengths and equal-slot flags, lane g holding pair g's
+    const uint32_t my_len = j + 1 < N ? G.sw_len[j] : 0u;
+    const uint32_t my_eq = j + 1 < N ? (uint32_t)G.sw_eq[j] : 0u;
     uint64_t any = 0;
     for (uint32_t g = 0; g + 1 < N; ++g) {
-        const int32_t nx_sp = G.E[((g + 1) * 64 + j) * 2 + 0];
-        const int32_t nx_t = G.E[((g + 1) * 64 + j) * 2 + 1];
-        const uint32_t nx_w = G.walker[(g + 1) * 64 + j];
+        const int32_t nx_sp = s_sp[g + 1][j];
+        const int32_t nx_t = s_t[g + 1][j];
+        const uint32_t nx_w = s_w[g + 1][j];
         const int32_t D = G.exch_all ? (nx_sp + nx_t) - (cur_sp + cur_t) : nx_t - cur_t;
         bool accept;
-        if (G.sw_eq[g] || D >= 0) {
+        const uint32_t len = __builtin_amdgcn_readlane(my_len, g);
+        if (__builtin_amdgcn_readlane(my_eq, g) || D >= 0) {
             accept = true;
         } else {
             const uint32_t m = (uint32_t)(-D) >> 2;
-            const uint32_t th = (m >= 1 && m <= G.sw_len[g]) ? G.sw_thr[(size_t)g * G.sw_cap + (m - 1)] : 0u;
+            const uint32_t th = (m >= 1 && m <= len) ? G.sw_thr[(size_t)g * G.sw_cap + (m - 1)] : 0u;
             const uint4 o = philox(make_uint4(j >> 2, p, (1u << 24) | g, G.gid), G.key0, G.key1);
             const uint32_t sel = j & 3u;
             const uint32_t r = sel == 0 ? o.x : sel == 1 ? o.y : sel == 2 ? o.z : o.w;
@@ -749,32 +761,40 @@ __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
         }
         const uint64_t mask = __ballot((int)accept);
         if (accept) {  // slot g takes the next configuration; cur moves up
-            G.E[(g * 64 + j) * 2 + 0] = nx_sp;
-            G.E[(g * 64 + j) * 2 + 1] = nx_t;
-            G.walker[g * 64 + j] = nx_w;
+            s_sp[g][j] = nx_sp;
+            s_t[g][j] = nx_t;
+            s_w[g][j] = nx_w;
         } else {       // cur stays at g; the next one becomes cur
-            G.E[(g * 64 + j) * 2 + 0] = cur_sp;
-            G.E[(g * 64 + j) * 2 + 1] = cur_t;
-            G.walker[g * 64 + j] = cur_w;
+            s_sp[g][j] = cur_sp;
+            s_t[g][j] = cur_t;
+            s_w[g][j] = cur_w;
             cur_sp = nx_sp;
             cur_t = nx_t;
             cur_w = nx_w;
         }
-        if (j == 0) {
-            G.swaplog[(size_t)(p % G.log_cap) * (N - 1) + g] = mask;
-            G.acc[g] += (uint64_t)__popcll(mask);
-            G.lastmask[g] = mask;
-        }
+        if (j == 0) s_mask[g] = mask;
         any |= mask;
     }
-    G.E[((N - 1) * 64 + j) * 2 + 0] = cur_sp;
-    G.E[((N - 1) * 64 + j) * 2 + 1] = cur_t;
-    G.walker[(N - 1) * 64 + j] = cur_w;
+    s_sp[N - 1][j] = cur_sp;
+    s_t[N - 1][j] = cur_t;
+    s_w[N - 1][j] = cur_w;
+    for (uint32_t g = 0; g < N; ++g) {
+        G.E[(g * 64 + j) * 2 + 0] = s_sp[g][j];
+        G.E[(g * 64 + j) * 2 + 1] = s_t[g][j];
+        G.walker[g * 64 + j] = s_w[g][j];
+    }
+    __syncthreads();  // s_mask complete (one wave: cheap)
+    if (j + 1 < N) {
+        const uint64_t mask = s_mask[j];
+        G.swaplog[(size_t)(p % G.log_cap) * (N - 1) + j] = mask;
+        G.acc[j] += (uint64_t)__popcll(mask);
+        G.lastmask[j] = mask;
+    }
     if (j == 0) G.lastmask[N - 1] = any ? 1ull : 0ull;
 
     // round trips 0 -> N-1 -> 0; this step ends at PT time p+1
     const uint32_t now = p + 1;
-    RoundTrip& r0 = G.rt[G.walker[j] * 64 + j];
+    RoundTrip& r0 = G.rt[s_w[0][j] * 64 + j];
     if (r0.state == 2) {
         r0.count += 1;
         r0.sum += (uint64_t)(now - r0.t_last);
@@ -784,7 +804,7 @@ __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
         r0.t_last = now;
         r0.state = 1;
     }
-    RoundTrip& rtop = G.rt[G.walker[(N - 1) * 64 + j] * 64 + j];
+    RoundTrip& rtop = G.rt[s_w[N - 1][j] * 64 + j];
     if (rtop.state == 1) rtop.state = 2;
 }
 
