@@ -222,18 +222,31 @@ def test_correlations_of_the_L5_ground_state():
     assert got["Q2"] > got["F"] > 0
 
 
-def test_monte_carlo_slices_follow_the_transfer_matrix_ground_state():
-    """The consistency check of MCQSG against EDQSG (App. E): in a long
-    periodic prism a slice is distributed as psi(S)^2, psi the leading
-    eigenvector of the symmetric transfer matrix, so the Monte Carlo mean of
-    the space bond sum per slice equals sum_n v_n^2 Bsp(n) over the even
-    sector (corrections ~ (lambda_odd / lambda_even)^L_tau, negligible at
-    L_tau = 64).  Chain on the device (paper's equal-coupling form, k = 0.31
-    on two equal slots, 64 replicas each), transfer matrix and Lanczos on the
-    device; the comparison is statistical: within 5 standard errors of batch
-    means, while a coupling 0.02 away is many errors off."""
+@pytest.mark.parametrize("form", ["k-ladder", "gamma"])
+def test_monte_carlo_slices_follow_the_transfer_matrix(form):
+    """The consistency check of MCQSG against EDQSG (App. E): in a periodic
+    prism of L_tau slices a slice is distributed as
+    sum_k lambda_k^L_tau psi_k(S)^2 / sum_k lambda_k^L_tau over the
+    eigenpairs of the symmetric transfer matrix; with the leading even and
+    the leading odd eigenpairs (the paper's finite-L_tau estimate) the Monte
+    Carlo mean of the space bond sum per slice is
+    (lambda_e^L_tau B_e + lambda_o^L_tau B_o) / (lambda_e^L_tau + lambda_o^L_tau),
+    B = sum_n v_n^2 Bsp(n), as long as the next even eigenvalue's weight is
+    negligible (checked).  Chain on the device on two equal slots, 64
+    replicas each: the paper's equal-coupling form (k = 0.31 on every bond,
+    odd weight ~1e-10 at L_tau = 64) or the two-coupling form (k = 0.31,
+    k_perp from Gamma = 1.2: odd weight ~0.11); transfer matrix and Lanczos
+    on the device.  Statistical: within 5 standard errors of batch means,
+    while a space coupling 0.02 away is many errors off."""
     L, L_tau, k = 4, 64, 0.31
-    g = W.Group(L, L_tau, 1.0, np.array([k, k]), 90, W.MC_SEED, [77] * 64, ladder="k")
+    if form == "k-ladder":
+        g = W.Group(L, L_tau, 1.0, np.array([k, k]), 90, W.MC_SEED, [77] * 64, ladder="k")
+        kp = k
+    else:
+        gamma = 1.2
+        beta = k * L_tau
+        g = W.Group(L, L_tau, beta, np.array([gamma, gamma]), 91, W.MC_SEED, [77] * 64)
+        kp = -0.5 * np.log(np.tanh(beta * gamma / L_tau))
     with qsg.Ensemble([g], pt_every=10, swaplog_cap=8) as ens:
         ens.init_spins()
         ens.sweep(2000, qsg.QSG_BATCHED | qsg.QSG_GRAPH)
@@ -250,15 +263,24 @@ def test_monte_carlo_slices_follow_the_transfer_matrix_ground_state():
     err = float(np.std(batch_means, ddof=1) / np.sqrt(len(batch_means)))
     jx = 1 - 2 * (jx_w.astype(np.int64) & 1)
     jy = 1 - 2 * (jy_w.astype(np.int64) & 1)
+    B = None
 
-    def exact(kk):
-        d = qsg.tm_desc(L, kk, kk, jx, jy, 1)
-        v = qsg.tm_lanczos(d, 300, 1, 1e-12, seed=2, want_vector=True)["vector"].cpu().numpy()
-        p = v * v / np.dot(v, v)
-        B = transfer.slice_bond_sum(np.arange(v.size), L, jx, jy)
-        return float(np.dot(p, B))
+    def leading(kk, parity, n_eig):
+        d = qsg.tm_desc(L, kk, kp, jx, jy, parity)
+        r = qsg.tm_lanczos(d, 300, n_eig, 1e-12, seed=2, want_vector=True)
+        v = r["vector"].cpu().numpy()
+        return r["values"], float(np.dot(v * v / np.dot(v, v), B))
 
-    want = exact(k)
-    say(f"[mc vs transfer] <Bsp>/slice MC {mc:.5f} +- {err:.5f}, ground state {want:.5f}")
+    def predict(kk):
+        ev, be = leading(kk, 1, 2)
+        od, bo = leading(kk, -1, 1)
+        assert (ev[1] / ev[0]) ** L_tau < 1e-6  # the next even state does not count
+        wo = (od[0] / ev[0]) ** L_tau
+        return (be + wo * bo) / (1.0 + wo), wo
+
+    B = transfer.slice_bond_sum(np.arange(transfer.sector_dim(L)), L, jx, jy)
+    want, wo = predict(k)
+    say(f"[mc vs transfer] {form}: <Bsp>/slice MC {mc:.5f} +- {err:.5f}, transfer matrix "
+        f"{want:.5f} (odd-sector weight {wo:.3g})")
     assert abs(mc - want) < 5 * err + 1e-3
-    assert abs(exact(k + 0.02) - mc) > 10 * err
+    assert abs(predict(k + 0.02)[0] - mc) > 10 * err
