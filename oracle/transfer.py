@@ -220,3 +220,40 @@ def ground_correlations_wht(L: int, v: np.ndarray) -> Dict[str, float]:
 def xi2(Q2: float, F: float, L: int) -> float:
     """Second-moment correlation length (App. E): sqrt(Q2/F - 1) / (2 sin(pi/L))."""
     return math.sqrt(Q2 / F - 1.0) / (2.0 * math.sin(math.pi / L))
+
+
+def odd_weight(lam_even: float, lam_odd: float, L_tau: int) -> float:
+    """Weight of the odd sector's leading state in a periodic prism of L_tau
+    slices when only the two leading states are kept: lambda_o^L_tau /
+    (lambda_e^L_tau + lambda_o^L_tau); L_tau = 0 stands for infinity."""
+    if L_tau == 0:
+        return 0.0
+    return 1.0 / (1.0 + math.exp(L_tau * math.log(lam_even / lam_odd)))
+
+
+def correlations_mixed(L: int, v_even: np.ndarray, v_odd: np.ndarray, w: float) -> Dict[str, float]:
+    """Q2, Q4, F of the mixture (1 - w) |e><e| + w |o><o| of two unit-weight
+    sector states (App. E, the finite-L_tau estimates of EDQSG): M and R are
+    linear in the state's weights, so they mix, and Q2, Q4, F follow from the
+    mixed correlations as for one state (Walsh-Hadamard route)."""
+    from itertools import combinations
+    V = L * L
+    pe = np.asarray(v_even, dtype=np.float64) ** 2
+    po = np.asarray(v_odd, dtype=np.float64) ** 2
+    p = (1.0 - w) * pe / pe.sum() + w * po / po.sum()
+    Wt = walsh_hadamard(p)
+    Wt = Wt / Wt[0]
+    last = V - 1
+
+    def mask(s):
+        return sum(1 << i for i in s if i != last)
+
+    s2 = sF = 0.0
+    for x, y in combinations(range(V), 2):
+        r2 = Wt[mask((x, y))] ** 2
+        s2 += r2
+        sF += r2 * (math.cos(2 * math.pi * (x % L - y % L) / L) +
+                    math.cos(2 * math.pi * (x // L - y // L) / L))
+    s4 = sum(Wt[mask(q)] ** 2 for q in combinations(range(V), 4))
+    return {"Q2": V + 2 * s2, "Q4": 3 * V * V - 2 * V + (12 * V - 16) * s2 + 24 * s4,
+            "F": V + sF}

@@ -180,3 +180,28 @@ def test_ground_correlations_closed_forms(L):
     o = transfer.ground_correlations_wht(L, e)
     assert np.allclose([o["Q2"], o["Q4"]], [V * V, V ** 4], rtol=1e-12)
     assert abs(o["F"]) < 1e-9 * V * V
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_mixed_correlations(L):
+    """The finite-L_tau estimate mixes the two leading states' weights: at
+    w = 0 and w = 1 it is the one-state result, and for any w it equals the
+    definitions (all ordered pairs and quadruples) evaluated on the mixed
+    weights; the odd weight falls off as (lambda_o / lambda_e)^L_tau."""
+    rng = np.random.default_rng(40 + L)
+    N = transfer.sector_dim(L)
+    ve, vo = rng.standard_normal(N), 3.0 * rng.standard_normal(N)
+    for key in ("Q2", "Q4", "F"):
+        assert abs(transfer.correlations_mixed(L, ve, vo, 0.0)[key] -
+                   transfer.ground_correlations_wht(L, ve)[key]) < 1e-9
+        assert abs(transfer.correlations_mixed(L, ve, vo, 1.0)[key] -
+                   transfer.ground_correlations_wht(L, vo)[key]) < 1e-9
+    w = 0.3
+    mix = np.sqrt((1 - w) * ve ** 2 / (ve ** 2).sum() + w * vo ** 2 / (vo ** 2).sum())
+    a = transfer.correlations_mixed(L, ve, vo, w)
+    b = transfer.ground_correlations(L, mix)
+    for key in ("Q2", "Q4", "F"):
+        assert abs(a[key] - b[key]) < 1e-10 * max(abs(b[key]), 1.0)
+    assert transfer.odd_weight(2.0, 1.0, 0) == 0.0
+    assert abs(transfer.odd_weight(2.0, 1.0, 3) - 1.0 / 9.0) < 1e-15
+    assert abs(transfer.odd_weight(1.0, 1.0, 50) - 0.5) < 1e-15
