@@ -350,6 +350,25 @@ size_t qsg_tm_correlations_workspace_bytes(uint32_t L);
 qsg_status qsg_tm_correlations(uint32_t L, const double* d_vec, void* d_ws, size_t ws_bytes,
                                double* out, void* hip_stream);
 
+/* Finite-L_tau estimates of the same correlations (paper: App. E; EDQSG
+ * reports them for a list of Euclidean lengths): a slice of the periodic
+ * prism of L_tau slices sees the two leading states, the even one d_even
+ * with eigenvalue lambda_even and the odd one d_odd with lambda_odd
+ * (sector vectors of qsg_tm_dim(L) doubles, device, any norm), mixed with
+ * the odd weight w = lambda_odd^L_tau / (lambda_even^L_tau +
+ * lambda_odd^L_tau); every correlation of the previous call becomes
+ * (1 - w) <e|..|e> + w <o|..|o> before it is squared.  l_taus: n lengths
+ * (host), 0 meaning L_tau -> infinity (w = 0, the result of
+ * qsg_tm_correlations on d_even).  out: 3n doubles (host), (Q2, Q4, F) per
+ * length; 1 <= n <= 4096.  The eigenvalues must be positive and finite
+ * (QSG_E_INVALID otherwise).  d_ws: qsg_tm_correlations_lt_workspace_bytes(L, n) bytes of
+ * device memory, caller owned.  Synchronises hip_stream. */
+size_t qsg_tm_correlations_lt_workspace_bytes(uint32_t L, uint32_t n);
+qsg_status qsg_tm_correlations_lt(uint32_t L, const double* d_even, const double* d_odd,
+                                  double lambda_even, double lambda_odd, const uint32_t* l_taus,
+                                  uint32_t n, void* d_ws, size_t ws_bytes, double* out,
+                                  void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Learned Gamma ladder: a 6 -> 128 -> 128 -> 128 -> 32 MLP (exact-erf GELU on
  * the hidden layers) mapping (L, L_tau, beta, frustrated-plaquette fraction,

@@ -228,7 +228,10 @@ def odd_weight(lam_even: float, lam_odd: float, L_tau: int) -> float:
     (lambda_e^L_tau + lambda_o^L_tau); L_tau = 0 stands for infinity."""
     if L_tau == 0:
         return 0.0
-    return 1.0 / (1.0 + math.exp(L_tau * math.log(lam_even / lam_odd)))
+    x = L_tau * math.log(lam_even / lam_odd)
+    if x > 0:  # the same ratio written so that a long prism does not overflow
+        return math.exp(-x) / (1.0 + math.exp(-x))
+    return 1.0 / (1.0 + math.exp(x))
 
 
 def correlations_mixed(L: int, v_even: np.ndarray, v_odd: np.ndarray, w: float) -> Dict[str, float]:

@@ -31,8 +31,8 @@ def _run(cmd, verbose):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src in ("qsg_kernels.hip", "qsg_overlaps.hip", "qsg_transfer.hip", "qsg_mlp.hip",
-                "qsg_api.cpp", "qsg_transfer_api.cpp"):
+    for src in ("qsg_kernels.hip", "qsg_overlaps.hip", "qsg_transfer.hip", "qsg_corr_mix.hip",
+                "qsg_mlp.hip", "qsg_api.cpp", "qsg_transfer_api.cpp"):
         obj = os.path.join(BUILD, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         _run(["hipcc", *HIP_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj], verbose)

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/qsg.h"
+#include "qsg_corr_mix.h"
 #include "qsg_transfer.h"
 
 namespace {
@@ -21,6 +22,7 @@ namespace {
 using qsg::TmParams;
 
 constexpr uint32_t kMaxLanczos = 4096;
+constexpr uint32_t kMaxLengths = 4096;  // Euclidean lengths per correlation call
 
 #define TM_HIP(expr)                                                                             \
     do {                                                                                         \
@@ -354,6 +356,73 @@ qsg_status qsg_tm_correlations(uint32_t L, const double* d_vec, void* d_ws, size
     out[0] = t.q2 + h[0];
     out[1] = t.q4 + h[1];
     out[2] = t.f + h[2];
+    return QSG_OK;
+}
+
+
+size_t qsg_tm_correlations_lt_workspace_bytes(uint32_t L, uint32_t n) {
+    const uint64_t N = qsg_tm_dim(L);
+    if (!N || n == 0 || n > kMaxLengths) return 0;
+    const size_t E = corr_entries(L);
+    return 2 * align256(N * sizeof(double)) + align256(E * sizeof(uint32_t)) +
+           align256(3 * E * sizeof(double)) + 2 * align256(3 * (size_t)n * sizeof(double));
+}
+
+qsg_status qsg_tm_correlations_lt(uint32_t L, const double* d_even, const double* d_odd,
+                                  double lambda_even, double lambda_odd, const uint32_t* l_taus,
+                                  uint32_t n, void* d_ws, size_t ws_bytes, double* out,
+                                  void* hip_stream) {
+    if (L > QSG_TM_MAX_L)
+        return qsg::report_error(QSG_E_UNSUPPORTED, "L = %u > %u", L, QSG_TM_MAX_L);
+    if (L < 2) return qsg::report_error(QSG_E_INVALID, "L = %u < 2", L);
+    if (n == 0 || n > kMaxLengths)
+        return qsg::report_error(QSG_E_INVALID, "%u lengths (1 .. %u)", n, kMaxLengths);
+    if (!d_even || !d_odd || !l_taus || !d_ws || !out)
+        return qsg::report_error(QSG_E_INVALID, "null buffer");
+    if (!(lambda_even > 0.0) || !(lambda_odd > 0.0) || !std::isfinite(lambda_even) ||
+        !std::isfinite(lambda_odd))
+        return qsg::report_error(QSG_E_INVALID, "eigenvalues %g, %g are not positive and finite",
+                                 lambda_even, lambda_odd);
+    if (ws_bytes < qsg_tm_correlations_lt_workspace_bytes(L, n))
+        return qsg::report_error(QSG_E_BUFFER, "workspace needs %zu bytes",
+                                 qsg_tm_correlations_lt_workspace_bytes(L, n));
+    // odd weight per length: 1 / (1 + (lambda_even / lambda_odd)^L_tau)
+    std::vector<double> w_odd(n);
+    const double log_ratio = std::log(lambda_even) - std::log(lambda_odd);
+    for (uint32_t i = 0; i < n; ++i)
+        w_odd[i] = l_taus[i] == 0 ? 0.0 : 1.0 / (1.0 + std::exp(l_taus[i] * log_ratio));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t N = (size_t)qsg_tm_dim(L);
+    const CorrTable t = corr_table(L);
+    const uint32_t E = (uint32_t)t.mask.size();
+    char* base = static_cast<char*>(d_ws);
+    double* We = reinterpret_cast<double*>(base);
+    double* Wo = reinterpret_cast<double*>(base + align256(N * sizeof(double)));
+    uint32_t* mask = reinterpret_cast<uint32_t*>(base + 2 * align256(N * sizeof(double)));
+    double* w = reinterpret_cast<double*>(reinterpret_cast<char*>(mask) +
+                                          align256(E * sizeof(uint32_t)));
+    double* wodd = reinterpret_cast<double*>(reinterpret_cast<char*>(w) +
+                                             align256(3 * (size_t)E * sizeof(double)));
+    double* sums = reinterpret_cast<double*>(reinterpret_cast<char*>(wodd) +
+                                             align256(3 * (size_t)n * sizeof(double)));
+    TmParams P;
+    std::memset(&P, 0, sizeof P);
+    P.L = L;
+    P.n = L * L - 1;
+    TM_HIP(qsg::launch_tm_wht_squares(P, d_even, We, s));
+    TM_HIP(qsg::launch_tm_wht_squares(P, d_odd, Wo, s));
+    TM_HIP(hipMemcpyAsync(mask, t.mask.data(), E * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    TM_HIP(hipMemcpyAsync(w, t.w.data(), 3 * (size_t)E * sizeof(double), hipMemcpyHostToDevice, s));
+    TM_HIP(hipMemcpyAsync(wodd, w_odd.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+    TM_HIP(qsg::launch_tm_corr_mixed(We, Wo, mask, w, E, wodd, n, sums, s));
+    std::vector<double> h(3 * (size_t)n);
+    TM_HIP(hipMemcpyAsync(h.data(), sums, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < n; ++i) {
+        out[3 * i] = t.q2 + h[3 * i];
+        out[3 * i + 1] = t.q4 + h[3 * i + 1];
+        out[3 * i + 2] = t.f + h[3 * i + 2];
+    }
     return QSG_OK;
 }
 

@@ -121,6 +121,10 @@ _SIGS = {
     "qsg_tm_correlations_workspace_bytes": (C.c_size_t, [C.c_uint32]),
     "qsg_tm_correlations": (C.c_int32, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t,
                                         C.c_void_p, C.c_void_p]),
+    "qsg_tm_correlations_lt_workspace_bytes": (C.c_size_t, [C.c_uint32, C.c_uint32]),
+    "qsg_tm_correlations_lt": (C.c_int32, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_double,
+                                           C.c_double, C.c_void_p, C.c_uint32, C.c_void_p,
+                                           C.c_size_t, C.c_void_p, C.c_void_p]),
     "qsg_mlp_param_count": (C.c_uint32, []),
     "qsg_mlp_workspace_floats": (C.c_size_t, [C.c_uint32]),
     "qsg_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
@@ -541,6 +545,36 @@ def tm_correlations(L: int, vec, stream=None) -> dict:
     q2, q4, f = (float(v) for v in out)
     xi = math.sqrt(q2 / f - 1.0) / (2.0 * math.sin(math.pi / L)) if f > 0 and q2 > f else float("nan")
     return {"Q2": q2, "Q4": q4, "F": f, "xi2": xi}
+
+
+def tm_correlations_lt(L: int, v_even, v_odd, lambda_even: float, lambda_odd: float,
+                       l_taus, stream=None) -> list:
+    """Finite-L_tau estimates of Q2, Q4, F from the leading even and odd
+    states (float64 device tensors of tm_dim(L) entries and their
+    eigenvalues) for each length in l_taus (0: L_tau -> infinity);
+    qsg_tm_correlations_lt.  One dict per length, as tm_correlations."""
+    import math
+    import torch
+    n = tm_dim(L)
+    for v in (v_even, v_odd):
+        if v.dtype != torch.float64 or not v.is_cuda or v.numel() != n or not v.is_contiguous():
+            raise ValueError(f"need contiguous float64 device tensors of {n} entries")
+    lt = np.ascontiguousarray(np.asarray(l_taus, dtype=np.uint32).reshape(-1))
+    nbytes = int(lib().qsg_tm_correlations_lt_workspace_bytes(L, len(lt)))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=v_even.device)
+    out = np.zeros(3 * max(len(lt), 1))
+    sp = C.c_void_p(stream.cuda_stream) if stream is not None else _stream_ptr()
+    _check(lib().qsg_tm_correlations_lt(L, C.c_void_p(v_even.data_ptr()),
+                                        C.c_void_p(v_odd.data_ptr()), float(lambda_even),
+                                        float(lambda_odd), _ptr(lt), len(lt),
+                                        C.c_void_p(ws.data_ptr()), nbytes, _ptr(out), sp))
+    res = []
+    for i in range(len(lt)):
+        q2, q4, f = (float(v) for v in out[3 * i:3 * i + 3])
+        xi = (math.sqrt(q2 / f - 1.0) / (2.0 * math.sin(math.pi / L))
+              if f > 0 and q2 > f else float("nan"))
+        res.append({"L_tau": int(lt[i]), "Q2": q2, "Q4": q4, "F": f, "xi2": xi})
+    return res
 
 
 def _torch_f64():

@@ -207,3 +207,33 @@ def test_correlations_sizes_and_validation_without_the_device():
                                      (3, dummy, dummy, 16, qsg.QSG_E_BUFFER)):
         rc = lib.qsg_tm_correlations(L, vec, ws, nbytes, out.ctypes.data, None)
         assert rc == want, (L, rc)
+
+
+def test_finite_length_correlations_validation_without_the_device():
+    from paper_2402_03920_amd import qsg
+    lib = qsg.lib()
+    assert lib.qsg_tm_correlations_lt_workspace_bytes(3, 0) == 0
+    assert lib.qsg_tm_correlations_lt_workspace_bytes(3, 4097) == 0
+    assert lib.qsg_tm_correlations_lt_workspace_bytes(6, 1) == 0
+    one = lib.qsg_tm_correlations_lt_workspace_bytes(3, 1)
+    assert one >= lib.qsg_tm_correlations_workspace_bytes(3) + 8 * lib.qsg_tm_dim(3)
+    assert lib.qsg_tm_correlations_lt_workspace_bytes(3, 100) > one
+    lt = np.array([0, 8, 64], dtype=np.uint32)
+    out = np.zeros(9)
+    dummy = C.c_void_p(1)  # never dereferenced: every case fails validation first
+    big = lib.qsg_tm_correlations_lt_workspace_bytes(3, 3)
+    cases = ((1, 1.0, 0.5, 3, big, qsg.QSG_E_INVALID),
+             (6, 1.0, 0.5, 3, big, qsg.QSG_E_UNSUPPORTED),
+             (3, 1.0, 0.5, 0, big, qsg.QSG_E_INVALID),
+             (3, 0.0, 0.5, 3, big, qsg.QSG_E_INVALID),
+             (3, 1.0, -0.5, 3, big, qsg.QSG_E_INVALID),
+             (3, float("inf"), 0.5, 3, big, qsg.QSG_E_INVALID),
+             (3, float("nan"), 0.5, 3, big, qsg.QSG_E_INVALID),
+             (3, 1.0, 0.5, 3, 16, qsg.QSG_E_BUFFER))
+    for L, le, lo, n, nbytes, want in cases:
+        rc = lib.qsg_tm_correlations_lt(L, dummy, dummy, le, lo, lt.ctypes.data, n, dummy, nbytes,
+                                        out.ctypes.data, None)
+        assert rc == want, (L, le, lo, n, rc)
+    rc = lib.qsg_tm_correlations_lt(3, None, dummy, 1.0, 0.5, lt.ctypes.data, 3, dummy, big,
+                                    out.ctypes.data, None)
+    assert rc == qsg.QSG_E_INVALID

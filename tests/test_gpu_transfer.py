@@ -222,6 +222,61 @@ def test_correlations_of_the_L5_ground_state():
     assert got["Q2"] > got["F"] > 0
 
 
+LENGTHS = [0, 1, 2, 4, 16, 64, 1024, 4000000000]
+
+
+def check_mixed(L, ve, vo, le, lo, lengths):
+    got = qsg.tm_correlations_lt(L, torch.from_numpy(np.ascontiguousarray(ve)).cuda(),
+                                 torch.from_numpy(np.ascontiguousarray(vo)).cuda(), le, lo,
+                                 lengths)
+    assert [g["L_tau"] for g in got] == [int(t) for t in lengths]
+    for g, t in zip(got, lengths):
+        want = transfer.correlations_mixed(L, ve, vo, transfer.odd_weight(le, lo, int(t)))
+        for key in ("Q2", "Q4", "F"):
+            assert abs(g[key] - want[key]) <= 1e-10 * max(abs(want[key]), 1.0), (L, t, key, g, want)
+    return got
+
+
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_finite_length_correlations_match_oracle(L):
+    """Finite-L_tau estimates (App. E) from the oracle's leading even and
+    odd states, scaled to other norms, over a list of lengths from 1 to
+    4e9 (0 = infinity): against the oracle's mixture; L_tau = 0 gives the
+    even state's own result, and a huge L_tau too."""
+    say(f"[tm correlations, finite L_tau] L={L}")
+    case = W.transfer_case(L, 0.31, 0.52, seed=41 + L)
+    e = transfer.leading_eigenpairs(L, case.k, case.k_perp, case.jx, case.jy, 1, 1)
+    o = transfer.leading_eigenpairs(L, case.k, case.k_perp, case.jx, case.jy, -1, 1)
+    le, lo = float(e["values"][0]), float(o["values"][0])
+    got = check_mixed(L, 3.0 * e["vector"], 0.5 * o["vector"], le, lo, LENGTHS)
+    one = device_correlations(L, e["vector"])
+    for g in (got[0], got[-1]):
+        for key in ("Q2", "Q4", "F"):
+            assert abs(g[key] - one[key]) <= 1e-12 * max(abs(one[key]), 1.0)
+    # the odd state's weight falls with L_tau, and so do the estimates' gaps
+    w = [transfer.odd_weight(le, lo, t) for t in LENGTHS[1:-1]]
+    assert all(a > b for a, b in zip(w, w[1:])) and w[0] > 0.25
+    # equal eigenvalues: the half-and-half mixture at every finite length
+    half = check_mixed(L, e["vector"], o["vector"], 2.0, 2.0, [1, 7, 64])
+    assert all(abs(h["Q2"] - half[0]["Q2"]) <= 1e-12 * half[0]["Q2"] for h in half)
+
+
+def test_finite_length_correlations_L5():
+    """L = 5: the Lanczos leading states of both sectors, at three lengths,
+    against the oracle's mixture on the same vectors (copied back)."""
+    case = W.transfer_case()
+    vecs, lams = [], []
+    for parity in (1, -1):
+        d = qsg.tm_desc(case.L, case.k, case.k_perp, case.jx, case.jy, parity)
+        r = qsg.tm_lanczos(d, 300, 1, 1e-9, seed=7, want_vector=True)
+        vecs.append(r["vector"].cpu().numpy())
+        lams.append(float(r["values"][0]))
+    say(f"[tm correlations, finite L_tau] L=5 lambda_e/lambda_o = {lams[0] / lams[1]:.6f}")
+    got = check_mixed(5, vecs[0], vecs[1], lams[0], lams[1], [0, 8, 64])
+    for g in got:
+        say(f"  L_tau {g['L_tau']}: Q2 {g['Q2']:.6f} Q4 {g['Q4']:.4f} F {g['F']:.6f}")
+
+
 @pytest.mark.parametrize("form", ["k-ladder", "gamma"])
 def test_monte_carlo_slices_follow_the_transfer_matrix(form):
     """The consistency check of MCQSG against EDQSG (App. E): in a periodic

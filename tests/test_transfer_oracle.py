@@ -205,3 +205,5 @@ def test_mixed_correlations(L):
     assert transfer.odd_weight(2.0, 1.0, 0) == 0.0
     assert abs(transfer.odd_weight(2.0, 1.0, 3) - 1.0 / 9.0) < 1e-15
     assert abs(transfer.odd_weight(1.0, 1.0, 50) - 0.5) < 1e-15
+    assert transfer.odd_weight(2.0, 1.0, 10 ** 9) == 0.0  # long prisms: no overflow
+    assert transfer.odd_weight(1.0, 2.0, 10 ** 9) == 1.0
