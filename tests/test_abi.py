@@ -237,3 +237,15 @@ def test_finite_length_correlations_validation_without_the_device():
     rc = lib.qsg_tm_correlations_lt(3, None, dummy, 1.0, 0.5, lt.ctypes.data, 3, dummy, big,
                                     out.ctypes.data, None)
     assert rc == qsg.QSG_E_INVALID
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No fallback: with the shared library absent every entry point raises
+    instead of computing anything on the host."""
+    from paper_2402_03920_amd import qsg
+    monkeypatch.setattr(qsg, "_lib", None)
+    monkeypatch.setattr(qsg, "LIB_PATH", str(tmp_path / "libqsg.so"))
+    with pytest.raises(ImportError, match="missing"):
+        qsg.lib()
+    with pytest.raises(ImportError):
+        qsg.tm_dim(3)
