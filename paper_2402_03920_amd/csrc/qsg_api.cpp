@@ -490,11 +490,14 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         pre_slots[i + 1] = pre_slots[i] + g.N;
         if (g.V > max_v) max_v = g.V;
     }
-    c->plan_sweep = {c->d_groups, at<uint32_t>(c, L.prefix_sweep), n_groups, pre_sweep[n_groups]};
-    c->plan_energy = {c->d_groups, at<uint32_t>(c, L.prefix_energy), n_groups,
-                      pre_energy[n_groups]};
-    c->plan_swap = {c->d_groups, at<uint32_t>(c, L.prefix_swap), n_groups, pre_swap[n_groups]};
-    c->plan_slots = {c->d_groups, at<uint32_t>(c, L.prefix_slots), n_groups, pre_slots[n_groups]};
+    c->plan_sweep = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_sweep), pre_sweep.data(),
+                                   n_groups);
+    c->plan_energy = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_energy),
+                                    pre_energy.data(), n_groups);
+    c->plan_swap = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_swap), pre_swap.data(),
+                                  n_groups);
+    c->plan_slots = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_slots), pre_slots.data(),
+                                   n_groups);
     c->fused_lds_words = max_v <= qsg::kFusedLdsMaxWords ? max_v : 0;
 
     auto bail = [&](qsg_status st) {

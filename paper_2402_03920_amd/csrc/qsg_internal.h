@@ -116,7 +116,26 @@ struct BatchPlan {
     const uint32_t* prefix;  // device array [n_groups + 1]
     uint32_t n_groups;
     uint32_t n_blocks;
+    // per_group > 0 when every group has exactly per_group blocks: a block
+    // then finds its group by one scalar division (span divides by
+    // per_group) instead of a search of `prefix`
+    uint32_t per_group;
+    Divisor span;
 };
+
+// The plan of a batched launch from the host copy of its prefix sums.
+inline BatchPlan make_plan(const GroupDev* groups, const uint32_t* d_prefix,
+                           const uint32_t* prefix, uint32_t n_groups) {
+    BatchPlan p{groups, d_prefix, n_groups, prefix[n_groups], 0, Divisor{0, 0}};
+    const uint32_t first = n_groups ? prefix[1] - prefix[0] : 0;
+    bool equal = first > 0;
+    for (uint32_t i = 1; equal && i < n_groups; ++i) equal = prefix[i + 1] - prefix[i] == first;
+    if (equal) {
+        p.per_group = first;
+        p.span = make_divisor(first);
+    }
+    return p;
+}
 hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,
                                      uint32_t t_add, hipStream_t s);
 hipError_t launch_energy_batched(const BatchPlan& plan, hipStream_t s);

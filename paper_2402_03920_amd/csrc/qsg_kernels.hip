@@ -493,16 +493,31 @@ __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ pref
     return lo;
 }
 
+// Group of block b of a batched launch and the block's index within that
+// group.  Groups of one size (the usual ensemble) take one scalar division;
+// otherwise a binary search of the prefix sums, a chain of dependent scalar
+// loads that delays every block's first spin load.
+struct BlockPlace {
+    uint32_t gi, local;
+};
+__device__ __forceinline__ BlockPlace locate(const BatchPlan& p, uint32_t b) {
+    if (p.per_group) {
+        const uint32_t gi = fast_div(b, p.span);
+        return {gi, b - gi * p.per_group};
+    }
+    const uint32_t gi = find_group(p.prefix, p.n_groups, b);
+    return {gi, b - p.prefix[gi]};
+}
+
 __global__ void __launch_bounds__(kSweepBlock)
-k_half_sweep_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
-                     uint32_t n_groups, uint32_t colour, const uint32_t* __restrict__ ctr,
+k_half_sweep_batched(const BatchPlan plan, uint32_t colour, const uint32_t* __restrict__ ctr,
                      uint32_t t_add) {
     __shared__ SweepQueue Q;
     const uint32_t t = __builtin_amdgcn_readfirstlane(ctr[0] + t_add);
     const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
-    const uint32_t gi = find_group(prefix, n_groups, b);
-    const GroupDev G = uniform_record(groups + gi);
-    const uint32_t local = __builtin_amdgcn_readfirstlane(b - prefix[gi]);
+    const BlockPlace at = locate(plan, b);
+    const GroupDev G = uniform_record(plan.groups + at.gi);
+    const uint32_t local = __builtin_amdgcn_readfirstlane(at.local);
     const uint32_t nb = sweep_blocks_per_slot(G.V);
     const uint32_t g = fast_div(local, G.div_blocks);  // local / nb on the scalar unit
     const uint32_t idx = (local - g * nb) * kSweepBlock + threadIdx.x;
@@ -517,14 +532,13 @@ k_half_sweep_batched(const GroupDev* __restrict__ groups, const uint32_t* __rest
 // at most `lds_words` words are copied into LDS for the chunk.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kSweepBlock)
-k_chunk_fused(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ slot_prefix,
-              uint32_t n_groups, const uint32_t* __restrict__ ctr, uint32_t n_sweeps,
+k_chunk_fused(const BatchPlan slots, const uint32_t* __restrict__ ctr, uint32_t n_sweeps,
               uint32_t lds_words) {
     extern __shared__ uint64_t lds_spins[];
     __shared__ SweepQueue Q;
-    const uint32_t gi = find_group(slot_prefix, n_groups, blockIdx.x);
-    const GroupDev G = uniform_record(groups + gi);
-    const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x - slot_prefix[gi]);
+    const BlockPlace at = locate(slots, blockIdx.x);
+    const GroupDev G = uniform_record(slots.groups + at.gi);
+    const uint32_t g = __builtin_amdgcn_readfirstlane(at.local);
     const uint32_t V = G.V, half = V >> 1;
     uint64_t* Sg = G.spins + (size_t)g * V;
     const bool in_lds = V <= lds_words;
@@ -687,11 +701,10 @@ k_energy(const GroupDev G, int32_t* cnt) {
 }
 
 __global__ void __launch_bounds__(kEnergyBlock)
-k_energy_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
-                 uint32_t n_groups) {
-    const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
-    const GroupDev G = uniform_record(groups + gi);
-    const uint32_t local = blockIdx.x - prefix[gi];
+k_energy_batched(const BatchPlan plan) {
+    const BlockPlace at = locate(plan, blockIdx.x);
+    const GroupDev G = uniform_record(plan.groups + at.gi);
+    const uint32_t local = at.local;
     const uint32_t nb = energy_blocks_per_slot(G.V, kEnergyWords);
     const uint32_t g = local / nb;
     energy_block<kEnergyWords>(G, g, local - g * nb, G.cnt);
@@ -857,12 +870,11 @@ __global__ void __launch_bounds__(kSwapBlock) k_swap_apply(const GroupDev G) {
 }
 
 __global__ void __launch_bounds__(kSwapBlock)
-k_swap_apply_batched(const GroupDev* __restrict__ groups, const uint32_t* __restrict__ prefix,
-                     uint32_t n_groups) {
-    const uint32_t gi = find_group(prefix, n_groups, blockIdx.x);
-    const GroupDev G = uniform_record(groups + gi);
+k_swap_apply_batched(const BatchPlan plan) {
+    const BlockPlace at = locate(plan, blockIdx.x);
+    const GroupDev G = uniform_record(plan.groups + at.gi);
     if (G.N < 2 || G.lastmask[G.N - 1] == 0) return;
-    const uint32_t site = (blockIdx.x - prefix[gi]) * kSwapBlock + threadIdx.x;
+    const uint32_t site = at.local * kSwapBlock + threadIdx.x;
     if (site < G.V) swap_site(G, site);
 }
 
@@ -1013,8 +1025,8 @@ hipError_t launch_philox_probe(uint32_t* out, uint32_t n, uint32_t blocks, uint6
 hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,
                                      uint32_t t_add, hipStream_t s) {
     if (plan.n_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_half_sweep_batched, dim3(plan.n_blocks), dim3(kSweepBlock), 0, s,
-                       plan.groups, plan.prefix, plan.n_groups, colour, ctr, t_add);
+    hipLaunchKernelGGL(k_half_sweep_batched, dim3(plan.n_blocks), dim3(kSweepBlock), 0, s, plan,
+                       colour, ctr, t_add);
     return hipGetLastError();
 }
 hipError_t launch_chunk_fused(const BatchPlan& slots, const uint32_t* ctr, uint32_t n_sweeps,
@@ -1026,15 +1038,14 @@ hipError_t launch_chunk_fused(const BatchPlan& slots, const uint32_t* ctr, uint3
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_chunk_fused, dim3(slots.n_blocks), dim3(kSweepBlock), lds, s, slots.groups,
-                       slots.prefix, slots.n_groups, ctr, n_sweeps, lds_words);
+    hipLaunchKernelGGL(k_chunk_fused, dim3(slots.n_blocks), dim3(kSweepBlock), lds, s, slots, ctr,
+                       n_sweeps, lds_words);
     return hipGetLastError();
 }
 
 hipError_t launch_energy_batched(const BatchPlan& plan, hipStream_t s) {
     if (plan.n_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_energy_batched, dim3(plan.n_blocks), dim3(kEnergyBlock), 0, s,
-                       plan.groups, plan.prefix, plan.n_groups);
+    hipLaunchKernelGGL(k_energy_batched, dim3(plan.n_blocks), dim3(kEnergyBlock), 0, s, plan);
     return hipGetLastError();
 }
 hipError_t launch_pt_batched(const GroupDev* groups, uint32_t n_groups, const uint32_t* ctr,
@@ -1049,8 +1060,7 @@ hipError_t launch_advance(uint32_t* ctr, uint32_t dt, uint32_t dp, hipStream_t s
 }
 hipError_t launch_swap_apply_batched(const BatchPlan& plan, hipStream_t s) {
     if (plan.n_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_swap_apply_batched, dim3(plan.n_blocks), dim3(kSwapBlock), 0, s,
-                       plan.groups, plan.prefix, plan.n_groups);
+    hipLaunchKernelGGL(k_swap_apply_batched, dim3(plan.n_blocks), dim3(kSwapBlock), 0, s, plan);
     return hipGetLastError();
 }
 
