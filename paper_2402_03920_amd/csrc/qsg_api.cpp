@@ -491,13 +491,13 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         if (g.V > max_v) max_v = g.V;
     }
     c->plan_sweep = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_sweep), pre_sweep.data(),
-                                   n_groups);
+                                   n_groups, c->gd.data());
     c->plan_energy = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_energy),
-                                    pre_energy.data(), n_groups);
+                                    pre_energy.data(), n_groups, c->gd.data());
     c->plan_swap = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_swap), pre_swap.data(),
-                                  n_groups);
+                                  n_groups, c->gd.data());
     c->plan_slots = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_slots), pre_slots.data(),
-                                   n_groups);
+                                   n_groups, c->gd.data());
     c->fused_lds_words = max_v <= qsg::kFusedLdsMaxWords ? max_v : 0;
 
     auto bail = [&](qsg_status st) {
@@ -884,10 +884,14 @@ qsg_status qsg_set_schedule(qsg_ctx* c, uint32_t group, uint32_t sweep_split) {
         return fail(c, QSG_E_INVALID, "sweep_split %u outside 1..16", sweep_split);
     GroupDev& g = c->gd[group];
     g.q_split = sweep_split;
-    // later launches (and the next graph capture) see the new record
+    // later launches (and the next graph capture) see the new record, in
+    // device memory and in the plans' copies
     QSG_HIP(c, hipMemcpyAsync(c->d_groups + group, &g, sizeof(GroupDev), hipMemcpyHostToDevice,
                               c->stream));
     QSG_HIP(c, hipStreamSynchronize(c->stream));
+    const uint32_t n = (uint32_t)c->gd.size();
+    for (qsg::BatchPlan* p : {&c->plan_sweep, &c->plan_energy, &c->plan_swap, &c->plan_slots})
+        qsg::set_plan_shape(*p, c->gd.data(), n);
     destroy_graph(c);
     return QSG_OK;
 }

@@ -109,8 +109,7 @@ hipError_t launch_philox_probe(uint32_t* out, uint32_t n, uint32_t blocks, uint6
                               hipStream_t s);
 
 // Batched: one launch per pass over all groups.  `prefix[i]` is the first
-// block of group i (prefix[n_groups] = total blocks); a block finds its
-// group by a uniform binary search.
+// block of group i (prefix[n_groups] = total blocks).
 struct BatchPlan {
     const GroupDev* groups;  // device array [n_groups]
     const uint32_t* prefix;  // device array [n_groups + 1]
@@ -121,12 +120,60 @@ struct BatchPlan {
     // per_group) instead of a search of `prefix`
     uint32_t per_group;
     Divisor span;
+    // same_shape != 0 when every group's record equals `first` up to its
+    // Philox identity (gid, key0, key1) and pointers that advance by
+    // `stride` bytes from one group to the next: a block then builds its
+    // record from this kernel argument instead of loading it first
+    uint32_t same_shape;
+    uint64_t stride;
+    GroupDev first;
 };
 
-// The plan of a batched launch from the host copy of its prefix sums.
+// Record i with its pointers moved back by `shift` bytes and its Philox
+// identity cleared: equal for all groups of one shape (shift = i * stride).
+inline bool same_but_identity(const GroupDev& a, const GroupDev& b, uint64_t shift) {
+    auto ptr = [shift](const void* p, const void* q) {
+        return (uint64_t)(uintptr_t)p == (uint64_t)(uintptr_t)q + shift;
+    };
+    auto div = [](Divisor x, Divisor y) { return x.m == y.m && x.s == y.s; };
+    return a.L == b.L && a.Ltau == b.Ltau && a.N == b.N && a.V == b.V && a.sw_cap == b.sw_cap &&
+           a.log_cap == b.log_cap && a.q_split == b.q_split && a.exch_all == b.exch_all &&
+           a.anti == b.anti && div(a.div_half_plane, b.div_half_plane) &&
+           div(a.div_half_row, b.div_half_row) && div(a.div_plane, b.div_plane) &&
+           div(a.div_row, b.div_row) && div(a.div_blocks, b.div_blocks) &&
+           ptr(a.spins, b.spins) && ptr(a.Jx, b.Jx) && ptr(a.Jy, b.Jy) && ptr(a.jseed, b.jseed) &&
+           ptr(a.thr, b.thr) && ptr(a.sw_thr, b.sw_thr) && ptr(a.sw_len, b.sw_len) &&
+           ptr(a.sw_eq, b.sw_eq) && ptr(a.cnt, b.cnt) && ptr(a.E, b.E) &&
+           ptr(a.walker, b.walker) && ptr(a.rt, b.rt) && ptr(a.acc, b.acc) &&
+           ptr(a.swaplog, b.swaplog) && ptr(a.sums, b.sums) && ptr(a.lastmask, b.lastmask) &&
+           ptr(a.meas, b.meas) && ptr(a.hist, b.hist);
+}
+
+// Set the plan's shared-shape fields from the host copy of the records
+// (again whenever a record changes).
+inline void set_plan_shape(BatchPlan& p, const GroupDev* records, uint32_t n_groups) {
+    p.same_shape = 0;
+    p.stride = 0;
+    p.first = GroupDev{};
+    if (n_groups == 0) return;
+    const uint64_t base = (uint64_t)(uintptr_t)records[0].spins;
+    const uint64_t stride = n_groups > 1 ? (uint64_t)(uintptr_t)records[1].spins - base : 0;
+    for (uint32_t i = 0; i < n_groups; ++i)
+        if (!same_but_identity(records[i], records[0], (uint64_t)i * stride)) return;
+    p.same_shape = 1;
+    p.stride = stride;
+    p.first = records[0];
+}
+
+// The plan of a batched launch from the host copy of its prefix sums and
+// of the group records.
 inline BatchPlan make_plan(const GroupDev* groups, const uint32_t* d_prefix,
-                           const uint32_t* prefix, uint32_t n_groups) {
-    BatchPlan p{groups, d_prefix, n_groups, prefix[n_groups], 0, Divisor{0, 0}};
+                           const uint32_t* prefix, uint32_t n_groups, const GroupDev* records) {
+    BatchPlan p{};
+    p.groups = groups;
+    p.prefix = d_prefix;
+    p.n_groups = n_groups;
+    p.n_blocks = prefix[n_groups];
     const uint32_t first = n_groups ? prefix[1] - prefix[0] : 0;
     bool equal = first > 0;
     for (uint32_t i = 1; equal && i < n_groups; ++i) equal = prefix[i + 1] - prefix[i] == first;
@@ -134,6 +181,7 @@ inline BatchPlan make_plan(const GroupDev* groups, const uint32_t* d_prefix,
         p.per_group = first;
         p.span = make_divisor(first);
     }
+    set_plan_shape(p, records, n_groups);
     return p;
 }
 hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,

@@ -500,6 +500,46 @@ __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ pref
 struct BlockPlace {
     uint32_t gi, local;
 };
+// Record of group gi.  For groups of one shape (kSameShape: the plan's
+// same_shape, chosen at launch so that each instantiation has one path) it
+// is the kernel argument's copy with the pointers moved to group gi and the
+// group's own Philox identity: no load stands between the block's start and
+// its first address computation (the three identity words are needed only
+// later).  Otherwise the record is read from memory.
+template <typename T>
+__device__ __forceinline__ T* advance(T* p, uint64_t bytes) {
+    return (T*)((char*)p + bytes);
+}
+template <bool kSameShape>
+__device__ __forceinline__ GroupDev group_record(const BatchPlan& p, uint32_t gi) {
+    if (!kSameShape) return uniform_record(p.groups + gi);
+    GroupDev G = p.first;
+    const uint64_t d = (uint64_t)gi * p.stride;
+    G.spins = advance(G.spins, d);
+    G.Jx = advance(G.Jx, d);
+    G.Jy = advance(G.Jy, d);
+    G.jseed = advance(G.jseed, d);
+    G.thr = advance(G.thr, d);
+    G.sw_thr = advance(G.sw_thr, d);
+    G.sw_len = advance(G.sw_len, d);
+    G.sw_eq = advance(G.sw_eq, d);
+    G.cnt = advance(G.cnt, d);
+    G.E = advance(G.E, d);
+    G.walker = advance(G.walker, d);
+    G.rt = advance(G.rt, d);
+    G.acc = advance(G.acc, d);
+    G.swaplog = advance(G.swaplog, d);
+    G.sums = advance(G.sums, d);
+    G.lastmask = advance(G.lastmask, d);
+    G.meas = advance(G.meas, d);
+    G.hist = advance(G.hist, d);
+    const GroupDev* __restrict__ r = p.groups + gi;
+    G.gid = __builtin_amdgcn_readfirstlane(r->gid);
+    G.key0 = __builtin_amdgcn_readfirstlane(r->key0);
+    G.key1 = __builtin_amdgcn_readfirstlane(r->key1);
+    return G;
+}
+
 __device__ __forceinline__ BlockPlace locate(const BatchPlan& p, uint32_t b) {
     if (p.per_group) {
         const uint32_t gi = fast_div(b, p.span);
@@ -509,6 +549,7 @@ __device__ __forceinline__ BlockPlace locate(const BatchPlan& p, uint32_t b) {
     return {gi, b - p.prefix[gi]};
 }
 
+template <bool kSameShape>
 __global__ void __launch_bounds__(kSweepBlock)
 k_half_sweep_batched(const BatchPlan plan, uint32_t colour, const uint32_t* __restrict__ ctr,
                      uint32_t t_add) {
@@ -516,7 +557,7 @@ k_half_sweep_batched(const BatchPlan plan, uint32_t colour, const uint32_t* __re
     const uint32_t t = __builtin_amdgcn_readfirstlane(ctr[0] + t_add);
     const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
     const BlockPlace at = locate(plan, b);
-    const GroupDev G = uniform_record(plan.groups + at.gi);
+    const GroupDev G = group_record<kSameShape>(plan, at.gi);
     const uint32_t local = __builtin_amdgcn_readfirstlane(at.local);
     const uint32_t nb = sweep_blocks_per_slot(G.V);
     const uint32_t g = fast_div(local, G.div_blocks);  // local / nb on the scalar unit
@@ -537,7 +578,7 @@ k_chunk_fused(const BatchPlan slots, const uint32_t* __restrict__ ctr, uint32_t 
     extern __shared__ uint64_t lds_spins[];
     __shared__ SweepQueue Q;
     const BlockPlace at = locate(slots, blockIdx.x);
-    const GroupDev G = uniform_record(slots.groups + at.gi);
+    const GroupDev G = group_record<false>(slots, at.gi);
     const uint32_t g = __builtin_amdgcn_readfirstlane(at.local);
     const uint32_t V = G.V, half = V >> 1;
     uint64_t* Sg = G.spins + (size_t)g * V;
@@ -703,7 +744,7 @@ k_energy(const GroupDev G, int32_t* cnt) {
 __global__ void __launch_bounds__(kEnergyBlock)
 k_energy_batched(const BatchPlan plan) {
     const BlockPlace at = locate(plan, blockIdx.x);
-    const GroupDev G = uniform_record(plan.groups + at.gi);
+    const GroupDev G = group_record<false>(plan, at.gi);
     const uint32_t local = at.local;
     const uint32_t nb = energy_blocks_per_slot(G.V, kEnergyWords);
     const uint32_t g = local / nb;
@@ -872,7 +913,7 @@ __global__ void __launch_bounds__(kSwapBlock) k_swap_apply(const GroupDev G) {
 __global__ void __launch_bounds__(kSwapBlock)
 k_swap_apply_batched(const BatchPlan plan) {
     const BlockPlace at = locate(plan, blockIdx.x);
-    const GroupDev G = uniform_record(plan.groups + at.gi);
+    const GroupDev G = group_record<false>(plan, at.gi);
     if (G.N < 2 || G.lastmask[G.N - 1] == 0) return;
     const uint32_t site = at.local * kSwapBlock + threadIdx.x;
     if (site < G.V) swap_site(G, site);
@@ -1025,8 +1066,12 @@ hipError_t launch_philox_probe(uint32_t* out, uint32_t n, uint32_t blocks, uint6
 hipError_t launch_half_sweep_batched(const BatchPlan& plan, uint32_t colour, const uint32_t* ctr,
                                      uint32_t t_add, hipStream_t s) {
     if (plan.n_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_half_sweep_batched, dim3(plan.n_blocks), dim3(kSweepBlock), 0, s, plan,
-                       colour, ctr, t_add);
+    if (plan.same_shape)
+        hipLaunchKernelGGL(k_half_sweep_batched<true>, dim3(plan.n_blocks), dim3(kSweepBlock), 0, s,
+                           plan, colour, ctr, t_add);
+    else
+        hipLaunchKernelGGL(k_half_sweep_batched<false>, dim3(plan.n_blocks), dim3(kSweepBlock), 0,
+                           s, plan, colour, ctr, t_add);
     return hipGetLastError();
 }
 hipError_t launch_chunk_fused(const BatchPlan& slots, const uint32_t* ctr, uint32_t n_sweeps,
