@@ -261,6 +261,28 @@ def test_plain_large_full_ensemble_sampled_groups():
         compare_state(ens, ogs, groups=pick)
 
 
+def test_one_shape_ensemble_record_path_equals_per_sample_launches():
+    """Eight samples of one shape with their own group ids and Monte Carlo
+    seeds: the batched colour pass that builds each group's record from the
+    first one (moved pointers, own Philox identity) follows the per-sample
+    launches' trajectory, and so does the batched path that reads the
+    records from memory once one group's schedule differs."""
+    from dataclasses import replace
+    groups = [replace(g, mc_seed=1000 + 17 * i) for i, g in enumerate(W.plain_large().groups[:8])]
+    states = {}
+    for mode, odd_schedule in (("plain", False), ("graph", False), ("graph", True)):
+        say(f"[parity] one-shape ensemble, mode={mode}, one schedule differs={odd_schedule}")
+        with qsg.Ensemble(groups, pt_every=10, swaplog_cap=4) as ens:
+            if odd_schedule:
+                ens.set_schedule(5, 16)
+            ens.init_spins()
+            ens.sweep(20, MODES[mode])
+            states[(mode, odd_schedule)] = ens.get_state()
+    want = states[("plain", False)]
+    assert np.array_equal(states[("graph", False)], want)
+    assert np.array_equal(states[("graph", True)], want)
+
+
 def test_uneven_full_ensemble_sampled_groups():
     """All 256 uneven samples in one batched launch per pass, 20 sweeps with
     PT every 10; three of the smaller samples compared with the oracle."""
