@@ -877,6 +877,12 @@ qsg_status qsg_build_tables_k(uint32_t n_gamma, const double* k, uint32_t cap, u
     return QSG_OK;
 }
 
+// qsg::same_but_identity lists every field of the group record and the
+// kernels' group_record moves every pointer: a new field must be added to
+// both.
+static_assert(sizeof(GroupDev) == 12 * 4 + 5 * sizeof(qsg::Divisor) + 18 * sizeof(void*),
+              "GroupDev changed: update same_but_identity and group_record");
+
 qsg_status qsg_set_schedule(qsg_ctx* c, uint32_t group, uint32_t sweep_split) {
     if (qsg_status st = check_ctx(c)) return st;
     if (group >= c->gd.size()) return fail(c, QSG_E_INVALID, "group %u out of range", group);
