@@ -55,6 +55,7 @@ struct GroupLayout {
 struct Layout {
     std::vector<GroupLayout> g;
     Region groups_dev, prefix_sweep, prefix_energy, prefix_swap, prefix_slots, counters;
+    Region block_map;  // colour-pass block -> (group, block in group), unequal groups only
     size_t total = 0;
 };
 
@@ -135,6 +136,18 @@ bool make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config& cfg,
         g.hist = take(N * qsg::kHistBins * 4);
         L.g.push_back(g);
     }
+    // the colour pass's block map, when the groups' block counts differ
+    std::vector<uint64_t> blocks(n);
+    for (uint32_t i = 0; i < n; ++i)
+        blocks[i] = (uint64_t)d[i].n_gamma *
+                    qsg::sweep_blocks_per_slot(d[i].L * d[i].L * d[i].L_tau);
+    bool equal = true;
+    uint64_t total_blocks = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        equal = equal && blocks[i] == blocks[0];
+        total_blocks += blocks[i];
+    }
+    L.block_map = take(equal ? 0 : total_blocks * sizeof(qsg::BlockEntry));
     L.total = off;
     *out = std::move(L);
     return true;
@@ -525,6 +538,21 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
                               hipMemcpyHostToDevice, s));
     CREATE_HIP(hipMemcpyAsync(const_cast<uint32_t*>(c->plan_slots.prefix), pre_slots.data(),
                               4 * (n_groups + 1), hipMemcpyHostToDevice, s));
+    std::vector<qsg::BlockEntry> block_map;
+    if (L.block_map.bytes) {
+        block_map.reserve(pre_sweep[n_groups]);
+        for (uint32_t i = 0; i < n_groups; ++i)
+            for (uint32_t b = 0; b < pre_sweep[i + 1] - pre_sweep[i]; ++b) block_map.push_back({i, b});
+        if (block_map.size() * sizeof(qsg::BlockEntry) != L.block_map.bytes) {
+            fail(c, QSG_E_INVALID, "block map of %zu entries does not fill its region",
+                 block_map.size());
+            return bail(QSG_E_INVALID);
+        }
+        auto* d_map = at<qsg::BlockEntry>(c, L.block_map);
+        CREATE_HIP(hipMemcpyAsync(d_map, block_map.data(), L.block_map.bytes,
+                                  hipMemcpyHostToDevice, s));
+        c->plan_sweep.block_map = d_map;
+    }
     const uint32_t zero2[2] = {0, 0};
     CREATE_HIP(hipMemcpyAsync(c->d_counters, zero2, sizeof zero2, hipMemcpyHostToDevice, s));
     for (uint32_t i = 0; i < n_groups; ++i) {

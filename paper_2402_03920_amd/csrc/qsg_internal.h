@@ -110,9 +110,18 @@ hipError_t launch_philox_probe(uint32_t* out, uint32_t n, uint32_t blocks, uint6
 
 // Batched: one launch per pass over all groups.  `prefix[i]` is the first
 // block of group i (prefix[n_groups] = total blocks).
+// Group of a block and the block's index within the group.
+struct BlockEntry {
+    uint32_t gi, local;
+};
+
 struct BatchPlan {
     const GroupDev* groups;  // device array [n_groups]
     const uint32_t* prefix;  // device array [n_groups + 1]
+    // optional device array [n_blocks]: every block's group and index in
+    // it, so that a block of an ensemble of unequal groups finds its group
+    // with one load instead of a search of `prefix`
+    const BlockEntry* block_map;
     uint32_t n_groups;
     uint32_t n_blocks;
     // per_group > 0 when every group has exactly per_group blocks: a block

@@ -495,8 +495,9 @@ __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ pref
 
 // Group of block b of a batched launch and the block's index within that
 // group.  Groups of one size (the usual ensemble) take one scalar division;
-// otherwise a binary search of the prefix sums, a chain of dependent scalar
-// loads that delays every block's first spin load.
+// otherwise one load from the plan's block map where it has one, else a
+// binary search of the prefix sums (a chain of dependent scalar loads that
+// delays every block's first spin load).
 struct BlockPlace {
     uint32_t gi, local;
 };
@@ -540,10 +541,18 @@ __device__ __forceinline__ GroupDev group_record(const BatchPlan& p, uint32_t gi
     return G;
 }
 
+// kSameShape: the plan's groups share one shape, so they have equal block
+// counts and only the division is compiled in.
+template <bool kSameShape>
 __device__ __forceinline__ BlockPlace locate(const BatchPlan& p, uint32_t b) {
-    if (p.per_group) {
+    if (kSameShape || p.per_group) {
         const uint32_t gi = fast_div(b, p.span);
         return {gi, b - gi * p.per_group};
+    }
+    if (p.block_map) {
+        const BlockEntry e = p.block_map[b];
+        return {(uint32_t)__builtin_amdgcn_readfirstlane(e.gi),
+                (uint32_t)__builtin_amdgcn_readfirstlane(e.local)};
     }
     const uint32_t gi = find_group(p.prefix, p.n_groups, b);
     return {gi, b - p.prefix[gi]};
@@ -556,7 +565,7 @@ k_half_sweep_batched(const BatchPlan plan, uint32_t colour, const uint32_t* __re
     __shared__ SweepQueue Q;
     const uint32_t t = __builtin_amdgcn_readfirstlane(ctr[0] + t_add);
     const uint32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
-    const BlockPlace at = locate(plan, b);
+    const BlockPlace at = locate<kSameShape>(plan, b);
     const GroupDev G = group_record<kSameShape>(plan, at.gi);
     const uint32_t local = __builtin_amdgcn_readfirstlane(at.local);
     const uint32_t nb = sweep_blocks_per_slot(G.V);
@@ -577,7 +586,7 @@ k_chunk_fused(const BatchPlan slots, const uint32_t* __restrict__ ctr, uint32_t 
               uint32_t lds_words) {
     extern __shared__ uint64_t lds_spins[];
     __shared__ SweepQueue Q;
-    const BlockPlace at = locate(slots, blockIdx.x);
+    const BlockPlace at = locate<false>(slots, blockIdx.x);
     const GroupDev G = group_record<false>(slots, at.gi);
     const uint32_t g = __builtin_amdgcn_readfirstlane(at.local);
     const uint32_t V = G.V, half = V >> 1;
@@ -743,7 +752,7 @@ k_energy(const GroupDev G, int32_t* cnt) {
 
 __global__ void __launch_bounds__(kEnergyBlock)
 k_energy_batched(const BatchPlan plan) {
-    const BlockPlace at = locate(plan, blockIdx.x);
+    const BlockPlace at = locate<false>(plan, blockIdx.x);
     const GroupDev G = group_record<false>(plan, at.gi);
     const uint32_t local = at.local;
     const uint32_t nb = energy_blocks_per_slot(G.V, kEnergyWords);
@@ -912,7 +921,7 @@ __global__ void __launch_bounds__(kSwapBlock) k_swap_apply(const GroupDev G) {
 
 __global__ void __launch_bounds__(kSwapBlock)
 k_swap_apply_batched(const BatchPlan plan) {
-    const BlockPlace at = locate(plan, blockIdx.x);
+    const BlockPlace at = locate<false>(plan, blockIdx.x);
     const GroupDev G = group_record<false>(plan, at.gi);
     if (G.N < 2 || G.lastmask[G.N - 1] == 0) return;
     const uint32_t site = at.local * kSwapBlock + threadIdx.x;
