@@ -493,14 +493,6 @@ __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ pref
     return lo;
 }
 
-// Group of block b of a batched launch and the block's index within that
-// group.  Groups of one size (the usual ensemble) take one scalar division;
-// otherwise one load from the plan's block map where it has one, else a
-// binary search of the prefix sums (a chain of dependent scalar loads that
-// delays every block's first spin load).
-struct BlockPlace {
-    uint32_t gi, local;
-};
 // Record of group gi.  For groups of one shape (kSameShape: the plan's
 // same_shape, chosen at launch so that each instantiation has one path) it
 // is the kernel argument's copy with the pointers moved to group gi and the
@@ -541,8 +533,16 @@ __device__ __forceinline__ GroupDev group_record(const BatchPlan& p, uint32_t gi
     return G;
 }
 
-// kSameShape: the plan's groups share one shape, so they have equal block
-// counts and only the division is compiled in.
+// Group of block b of a batched launch and the block's index within that
+// group.  Groups of one size (the usual ensemble) take one scalar division;
+// otherwise one load from the plan's block map where it has one, else a
+// binary search of the prefix sums (a chain of dependent scalar loads that
+// delays every block's first spin load).  kSameShape: the plan's groups
+// share one shape, so they have equal block counts and only the division is
+// compiled in.
+struct BlockPlace {
+    uint32_t gi, local;
+};
 template <bool kSameShape>
 __device__ __forceinline__ BlockPlace locate(const BatchPlan& p, uint32_t b) {
     if (kSameShape || p.per_group) {
