@@ -148,23 +148,47 @@ typedef struct {
     uint64_t sum;   /* sum of their durations, in PT steps               */
 } qsg_roundtrip;
 
-/* Bytes of device workspace needed for these groups. 0 on invalid input. */
+/* Bytes of device workspace needed for these groups (Sec. 2.1: the state of
+ * one MCQSG run -- spins of every ladder point, couplings, the precomputed
+ * acceptance factors -- here for n_groups groups side by side; App. A: the
+ * energy measurement and the PT random walk `history_betas` as per-slot
+ * counters, sums, walker labels and a swap log of cfg->swaplog_cap rows).
+ * groups: host array of n_groups descriptors; cfg: host run settings; both
+ * only read.  Returns 0 on any invalid input, and also for a group of more
+ * than 2^29 words per slot (L*L*L_tau > 2^29: the kernels address a slot
+ * with 32-bit byte offsets and hold bond sums in 32-bit integers). */
 size_t qsg_workspace_bytes(const qsg_group_desc* groups, uint32_t n_groups,
                            const qsg_run_config* cfg);
 
 /* Create a context over `d_workspace` (device pointer, 256-byte aligned,
  * >= qsg_workspace_bytes) on HIP stream `hip_stream` (hipStream_t, may be
  * NULL for the null stream).  Builds the couplings on the device from the
- * lane seeds; the ladder is unset until qsg_set_gamma_ladder (or
- * qsg_set_k_ladder for QSG_LADDER_K groups). */
+ * lane seeds (App. A: the couplings come from their own seed, separate from
+ * the seeds of the initial configuration and of the Monte Carlo numbers;
+ * here each lane's J_{i,d} = -1 iff bit 0 of word 0 of Philox4x32-10 with
+ * counter (x + L y, d, 3<<24, 0) under key j_seed[lane] is set, Sec. 2.1.1).
+ * The ladder is unset until qsg_set_gamma_ladder (or qsg_set_k_ladder for
+ * QSG_LADDER_K groups).  groups and cfg are host memory, read only; the
+ * workspace stays the caller's and must outlive the context.  *out is set
+ * only on success.  QSG_E_INVALID for a malformed descriptor, null or
+ * misaligned workspace; QSG_E_UNSUPPORTED for L*L*L_tau > 2^29 or more
+ * than 2^31 blocks in one pass; QSG_E_BUFFER if ws_bytes is too small;
+ * none of these touches the device. */
 qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups,
                       const qsg_run_config* cfg, void* d_workspace,
                       size_t ws_bytes, void* hip_stream, qsg_ctx** out);
 
-/* Set group `group`'s ladder: n_gamma host doubles, > 0, non-decreasing.
- * Builds the Metropolis and exchange thresholds in binary128 on the host
- * and uploads them.  QSG_E_UNSUPPORTED if an exchange table would exceed
- * swap_table_cap; QSG_E_INVALID for a group of ladder_kind QSG_LADDER_K. */
+/* Set group `group`'s ladder: n_gamma host doubles, > 0, non-decreasing
+ * (slot 0 = smallest transverse field; App. A: the number of transverse
+ * field values, App. C: the decreasing k list = increasing Gamma).  Builds
+ * the precomputed acceptance factors of Sec. 2.1 -- here integer thresholds
+ * thr = ceil(2^32 min(1, e^{-dE})) - 1 for the 15 classes (n_s, n_t) of
+ * every slot, and exchange thresholds for every possible time-bond change
+ * of every adjacent pair -- in binary128 on the host (App. C: the tables
+ * are built in 128-bit floating point) and uploads them on the context's
+ * stream, synchronising it.  QSG_E_UNSUPPORTED if an exchange table would
+ * exceed swap_table_cap; QSG_E_INVALID for a decreasing or non-positive
+ * ladder or a group of ladder_kind QSG_LADDER_K (nothing is changed). */
 qsg_status qsg_set_gamma_ladder(qsg_ctx* ctx, uint32_t group, const double* gamma);
 
 /* The same for a group of ladder_kind QSG_LADDER_K: n_gamma couplings k_g,
@@ -174,37 +198,80 @@ qsg_status qsg_set_gamma_ladder(qsg_ctx* ctx, uint32_t group, const double* gamm
  * for B[g+1] - B[g] = -4m with B = Bsp + Bt. */
 qsg_status qsg_set_k_ladder(qsg_ctx* ctx, uint32_t group, const double* k);
 
-/* Random initial spins (Philox counter (site, 0, 2<<24 | g, group_id)) for
- * every group; resets sweep/PT counters, walkers, round trips, sums. */
+/* Random initial spins for every group (App. A: the initial configuration
+ * has its own seed; here word (site, slot g) = o0 | o1<<32 of Philox4x32-10,
+ * Sec. 2.1.1, with counter (site, 0, 2<<24 | g, group_id) under mc_seed).
+ * Resets the sweep and PT counters, walkers (walker g at slot g), round
+ * trips, sums and histograms.  Enqueued on the context's stream and
+ * synchronised; QSG_E_DEVICE if a launch fails (the context is then
+ * failed). */
 qsg_status qsg_init_spins(qsg_ctx* ctx);
 
-/* n_sweeps sweeps of every group, with the PT steps that fall due.
- * With a deadline set, returns QSG_E_INTERRUPTED after the PT chunk during
- * which it passed; the state is then consistent and can be resumed. */
+/* n_sweeps sweeps of every group, with the PT steps that fall due (App. A:
+ * an elementary step is `ptfr` full-lattice sweeps, each a red then a blue
+ * sublattice update, followed by a parallel-tempering update; here ptfr =
+ * cfg->pt_every and a PT step follows sweep t when (t+1) % pt_every == 0;
+ * Sec. 2.1: checkerboard Metropolis with precomputed acceptance factors and
+ * the exchange probability min(1, e^{(c_g - c_{g+1}) D})).  The sweep and PT
+ * indices t, p are global per context and persist across calls and
+ * checkpoints.  flags: QSG_PLAIN, or QSG_BATCHED optionally with QSG_GRAPH,
+ * QSG_FUSED and QSG_NO_PT; every combination gives the same trajectory.
+ * Work is enqueued on the context's stream (asynchronous).  QSG_E_INVALID
+ * for unknown flags, QSG_E_STATE before a ladder is set for every group or
+ * before spins exist.  With a deadline set (qsg_set_deadline; Sec. 3: the
+ * MAXTIME alarm that stops a run cleanly), returns QSG_E_INTERRUPTED after
+ * the PT chunk during which it passed; the state is then consistent and can
+ * be resumed or checkpointed. */
 qsg_status qsg_sweep(qsg_ctx* ctx, uint32_t n_sweeps, uint32_t flags);
 
-/* One PT step now (outside the cadence), every group. */
+/* One PT step now (outside the cadence), every group: energies recomputed
+ * from the spins, then the exchanges of Sec. 2.1 for pairs g = 0..N-2 in
+ * order, each lane independently (lane j's number: word j&3 of Philox with
+ * counter (j>>2, p, 1<<24 | g, group_id)), then the accepted lanes'
+ * configurations moved between the two slots.  Advances the PT index p
+ * only.  Asynchronous on the context's stream; QSG_E_STATE as qsg_sweep. */
 qsg_status qsg_pt_swap(qsg_ctx* ctx);
 
-/* Copy a measurement (see QSG_M_*) to host memory; synchronises. */
+/* Copy a measurement (see QSG_M_*) to host memory (App. A: the online
+ * energy measurement and `history_betas`, the state of the PT random walk;
+ * App. E, the overlap of two replicas at equal times, tau1 = tau2).  `what`
+ * selects one QSG_M_* value; host_out receives the groups' arrays one after
+ * another in group order, with the layout given beside each selector.
+ * Synchronises the context's stream.  QSG_E_INVALID for an unknown
+ * selector or null buffer, QSG_E_BUFFER if `bytes` is too small (nothing is
+ * written), QSG_E_STATE for ENERGY/OVERLAP before spins exist. */
 qsg_status qsg_measure(qsg_ctx* ctx, uint32_t what, void* host_out, size_t bytes);
 
-/* Spins of one group, n_words = n_gamma * L_tau * L * L, layout above. */
+/* Spins of one group as host words, n_words = n_gamma * L_tau * L * L, in
+ * the layout above ([slot][tau][y][x], bit j = lane j, bit 1 <=> S = -1:
+ * App. D's bit convention).  get: synchronises, then copies; QSG_E_BUFFER
+ * if n_words is too small.  set: n_words must match exactly (QSG_E_INVALID
+ * otherwise); the stored energies and walkers are not recomputed -- the
+ * next PT step recomputes the energies from the spins. */
 qsg_status qsg_get_spins(qsg_ctx* ctx, uint32_t group, uint64_t* host, size_t n_words);
 qsg_status qsg_set_spins(qsg_ctx* ctx, uint32_t group, const uint64_t* host, size_t n_words);
 
-/* Couplings of one group: host Jx[L*L], Jy[L*L]. */
+/* Couplings of one group as built on the device (App. A, flagJ = 0: the
+ * couplings are generated from their seed): host Jx[L*L], Jy[L*L], index
+ * x + L*y, bit j = lane j, bit 1 <=> J = -1.  Synchronises. */
 qsg_status qsg_get_couplings(qsg_ctx* ctx, uint32_t group, uint64_t* jx, uint64_t* jy);
 
 /* Full checkpoint (spins, counters, energies, walkers, round trips, sums,
- * logs) to/from a host buffer of qsg_state_bytes(ctx) bytes.  No random
- * state exists: the generator is counter-based (Sec. 2.1.1 footnote). */
+ * logs, and the ladders for a consistency check) to/from a host buffer of
+ * qsg_state_bytes(ctx) bytes (App. A: a run is a back-up or a new run).  No
+ * random state exists: the generator is counter-based, its counters tied
+ * to the lattice update (Sec. 2.1.1), so a resumed run continues the same
+ * trajectory.  set: QSG_E_INVALID for a buffer of another context or
+ * another ladder (nothing changed).  Both synchronise the stream. */
 size_t qsg_state_bytes(const qsg_ctx* ctx);
 qsg_status qsg_get_state(qsg_ctx* ctx, void* host, size_t bytes);
 qsg_status qsg_set_state(qsg_ctx* ctx, const void* host, size_t bytes);
 
-/* Thresholds of one group as uploaded: thr[N][15] (index n_s*3+n_t),
- * swap_equal[N-1], swap_len[N-1], swap_thr[N-1][swap_table_cap]. */
+/* Thresholds of one group as uploaded (Sec. 2.1's precomputed acceptance
+ * factors, App. C's 128-bit construction): host arrays thr[N][15] (index
+ * n_s*3+n_t), swap_equal[N-1], swap_len[N-1], swap_thr[N-1][swap_table_cap]
+ * (entry m-1 of pair g: threshold for a change D = -4m); any pointer may be
+ * NULL to skip it.  Synchronises; QSG_E_STATE if the ladder is not set. */
 qsg_status qsg_get_tables(qsg_ctx* ctx, uint32_t group, uint32_t* thr,
                           uint8_t* swap_equal, uint32_t* swap_len, uint32_t* swap_thr);
 
@@ -219,26 +286,36 @@ qsg_status qsg_build_tables(double beta, uint32_t L_tau, uint32_t n_gamma,
 qsg_status qsg_build_tables_k(uint32_t n_gamma, const double* k, uint32_t cap, uint32_t* thr,
                               uint8_t* swap_equal, uint32_t* swap_len, uint32_t* swap_thr);
 
-/* Colour-pass schedule of one group (the autotuner's knob): Philox blocks
- * every word goes through before the words still undecided are packed into
- * fewer waves, 1..16 (16 = never).  Results do not depend on it. */
+/* Colour-pass schedule of one group (the autotuner's knob; no paper basis:
+ * it replaces the paper's threads-per-block argument of Sec. 3): Philox
+ * blocks every word goes through before the words still undecided are
+ * packed into fewer waves, 1..16 (16 = never).  Results do not depend on
+ * it.  Synchronises; QSG_E_INVALID outside 1..16 (nothing changed). */
 qsg_status qsg_set_schedule(qsg_ctx* ctx, uint32_t group, uint32_t sweep_split);
 
-/* Wall-clock deadline checked between PT chunks of qsg_sweep (0: due now,
- * so the next qsg_sweep stops after its first chunk); < 0 clears it. */
+/* Wall-clock deadline checked between PT chunks of qsg_sweep (Sec. 3: the
+ * MAXTIME value that stops a run cleanly before a batch limit): seconds
+ * from now; 0: due now, so the next qsg_sweep stops after its first chunk;
+ * < 0 clears it.  QSG_E_INVALID for NaN.  Touches no device state. */
 qsg_status qsg_set_deadline(qsg_ctx* ctx, double seconds_from_now);
 
-/* Synchronise the context's stream. */
+/* Synchronise the context's stream; QSG_E_DEVICE if queued work failed. */
 qsg_status qsg_sync(qsg_ctx* ctx);
 
-/* Message of the last failure of this context (or of creation if NULL). */
+/* Message of the last failure of this context (or, for NULL, of the last
+ * failed creation or context-free call of this thread).  The string is
+ * owned by the library and valid until the next call on the context. */
 const char* qsg_last_error(const qsg_ctx* ctx);
 
-/* Release host objects; the caller then frees the workspace. */
+/* Synchronise, then release the context's host objects and HIP graphs; the
+ * caller then frees the workspace.  NULL is ignored. */
 void qsg_destroy(qsg_ctx* ctx);
 
-/* Philox4x32-10 on the device, for known-answer checks: for i < n, out[4i..]
- * = Philox(ctr = in[6i..6i+3], key = in[6i+4..6i+5]).  Device pointers. */
+/* Philox4x32-10 on the device, for known-answer checks (Sec. 2.1.1: the
+ * paper's generator, Salmon et al.): for i < n, out[4i..] =
+ * Philox(ctr = in[6i..6i+3], key = in[6i+4..6i+5]).  Device pointers owned
+ * by the caller; asynchronous on hip_stream.  QSG_E_INVALID for null
+ * buffers, QSG_E_DEVICE if the launch fails. */
 qsg_status qsg_philox(const uint32_t* d_in, uint32_t* d_out, uint32_t n, void* hip_stream);
 
 /* Euclidean-time overlaps of the configurations now in slots first_slot ..

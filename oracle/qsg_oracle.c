@@ -333,21 +333,21 @@ static void pt_step(oracle_state *st, int *failed) {
     const int N = st->N;
     const size_t V = (size_t)st->L * st->L * st->Ltau;
     const uint32_t p = (uint32_t)st->counters[1];
-    if (N < 2) {
-        /* one slot: no exchange partner and no distinct end slots, so the
-         * step only advances the PT clock */
-        st->counters[1] = p + 1;
-        return;
-    }
 
-    /* Tracked sums must equal sums recomputed from the configuration. */
+    /* The measurement of App. A: tracked sums must equal sums recomputed
+     * from the configuration, and the recomputed values enter the per-step
+     * sums and histograms -- for every group, one slot included (the energy
+     * measurement does not depend on the exchange).  Slots are
+     * independent here, so OpenMP may split them. */
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
     for (int g = 0; g < N; ++g) {
         int64_t bs[64], bt[64], qq[32];
         recompute_B(&a, st->spins + (size_t)g * V, st->Jx, st->Jy, bs, bt);
         overlap_pairs(&a, st->spins + (size_t)g * V, qq);
         for (int j = 0; j < 64; ++j) {
             if (bs[j] != st->Bsp[g * 64 + j] || bt[j] != st->Bt[g * 64 + j])
-                *failed = 1;
+                bad = 1;
             st->sum_Bsp[g * 64 + j] += bs[j];
             st->sum_Bt[g * 64 + j] += bt[j];
             /* bt = V - 2u with u the number of unsatisfied time bonds */
@@ -358,6 +358,14 @@ static void pt_step(oracle_state *st, int *failed) {
             st->sum_q[g * 32 + q] += qq[q];
             st->sum_q2[g * 32 + q] += qq[q] * qq[q];
         }
+    }
+    if (bad) *failed = 1;
+
+    if (N < 2) {
+        /* one slot: no exchange partner and no pair of distinct end slots,
+         * so there is no exchange and no round trip */
+        st->counters[1] = p + 1;
+        return;
     }
 
     /* Pairs in ascending order; each decision sees the state left by the

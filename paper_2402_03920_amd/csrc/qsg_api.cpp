@@ -63,8 +63,17 @@ uint32_t swap_cap_of(const qsg_group_desc& d) {
     return d.swap_table_cap ? d.swap_table_cap : kDefaultSwapCap;
 }
 
-bool valid_desc(const qsg_group_desc& d, std::string* why) {
+// Largest slot, in words: the colour pass addresses a slot as a base pointer
+// plus a 32-bit byte offset, and per-lane bond sums and their differences
+// are held in 32-bit integers (|Bsp| <= 2V, |Bt| <= V), both exact up to
+// V = 2^29 words (4 GiB per slot).
+constexpr uint64_t kMaxSlotWords = 1ull << 29;
+
+// QSG_OK, or QSG_E_INVALID for a malformed descriptor, or QSG_E_UNSUPPORTED
+// for a well-formed one beyond the slot size the kernels address.
+qsg_status check_desc(const qsg_group_desc& d, std::string* why) {
     char buf[256];
+    qsg_status code = QSG_E_INVALID;
     if (d.L < 2 || d.L > 256 || (d.L & 1)) {
         std::snprintf(buf, sizeof buf, "L=%u must be even and in [2, 256]", d.L);
     } else if (d.L_tau < 2 || d.L_tau > 65536 || (d.L_tau & 1)) {
@@ -73,8 +82,6 @@ bool valid_desc(const qsg_group_desc& d, std::string* why) {
         std::snprintf(buf, sizeof buf, "beta must be finite and > 0");
     } else if (d.n_gamma < 1 || d.n_gamma > QSG_MAX_GAMMA) {
         std::snprintf(buf, sizeof buf, "n_gamma=%u must be in [1, %d]", d.n_gamma, QSG_MAX_GAMMA);
-    } else if ((uint64_t)d.L * d.L * d.L_tau > (1ull << 31)) {
-        std::snprintf(buf, sizeof buf, "L*L*L_tau too large");
     } else if (d.ladder_kind != QSG_LADDER_GAMMA && d.ladder_kind != QSG_LADDER_K) {
         std::snprintf(buf, sizeof buf, "ladder_kind=%u unknown", d.ladder_kind);
     } else if (d.tau_boundary != QSG_TAU_PERIODIC && d.tau_boundary != QSG_TAU_ANTIPERIODIC) {
@@ -83,15 +90,20 @@ bool valid_desc(const qsg_group_desc& d, std::string* why) {
         std::snprintf(buf, sizeof buf, "reserved field must be 0");
     } else if (swap_cap_of(d) > (1u << 24)) {
         std::snprintf(buf, sizeof buf, "swap_table_cap too large");
+    } else if ((uint64_t)d.L * d.L * d.L_tau > kMaxSlotWords) {
+        std::snprintf(buf, sizeof buf, "L*L*L_tau = %llu words per slot exceeds the limit 2^29",
+                      (unsigned long long)d.L * d.L * d.L_tau);
+        code = QSG_E_UNSUPPORTED;
     } else {
-        return true;
+        return QSG_OK;
     }
     if (why) *why = buf;
-    return false;
+    return code;
 }
 
-bool make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config& cfg, Layout* out,
-                 std::string* why) {
+// QSG_OK or the status of the first bad descriptor (with `why` set).
+qsg_status make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config& cfg,
+                       Layout* out, std::string* why) {
     Layout L;
     size_t off = 0;
     auto take = [&off](size_t bytes) {
@@ -108,9 +120,9 @@ bool make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config& cfg,
     L.prefix_swap = take(sizeof(uint32_t) * (n + 1));
     L.prefix_slots = take(sizeof(uint32_t) * (n + 1));
     for (uint32_t i = 0; i < n; ++i) {
-        if (!valid_desc(d[i], why)) {
+        if (qsg_status st = check_desc(d[i], why)) {
             if (why) *why = "group " + std::to_string(i) + ": " + *why;
-            return false;
+            return st;
         }
         const size_t N = d[i].n_gamma, P = (size_t)d[i].L * d[i].L;
         const size_t V = P * d[i].L_tau;
@@ -147,10 +159,23 @@ bool make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config& cfg,
         equal = equal && blocks[i] == blocks[0];
         total_blocks += blocks[i];
     }
+    // every pass launches one grid over all groups: its block count must be
+    // a valid grid size and fit the 32-bit block prefix sums
+    uint64_t energy_blocks = 0, swap_blocks = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t V = d[i].L * d[i].L * d[i].L_tau;
+        energy_blocks += (uint64_t)d[i].n_gamma * qsg::energy_blocks_per_slot(V, qsg::kEnergyWords);
+        swap_blocks += qsg::swap_blocks(V);
+    }
+    if (total_blocks >= (1ull << 31) || energy_blocks >= (1ull << 31) ||
+        swap_blocks >= (1ull << 31)) {
+        if (why) *why = "the groups together need more than 2^31 blocks in one pass";
+        return QSG_E_UNSUPPORTED;
+    }
     L.block_map = take(equal ? 0 : total_blocks * sizeof(qsg::BlockEntry));
     L.total = off;
     *out = std::move(L);
-    return true;
+    return QSG_OK;
 }
 
 // Which specialised class list covers every class of this slot that is not
@@ -291,7 +316,6 @@ qsg_status plain_sweep(qsg_ctx* c, uint32_t t_add) {
 
 qsg_status plain_pt(qsg_ctx* c, uint32_t p_add) {
     for (const GroupDev& g : c->gd) {
-        if (g.N < 2) continue;
         QSG_HIP(c, qsg::launch_energy(g, g.cnt, c->stream));
         QSG_HIP(c, qsg::launch_pt(g, c->d_counters, p_add, c->stream));
         QSG_HIP(c, qsg::launch_swap_apply(g, c->stream));
@@ -310,12 +334,6 @@ qsg_status batched_pt(qsg_ctx* c, hipStream_t s, uint32_t p_add) {
     QSG_HIP(c, qsg::launch_pt_batched(c->d_groups, (uint32_t)c->gd.size(), c->d_counters, p_add, s));
     QSG_HIP(c, qsg::launch_swap_apply_batched(c->plan_swap, s));
     return QSG_OK;
-}
-
-bool any_pt(const qsg_ctx* c) {
-    for (const auto& g : c->gd)
-        if (g.N >= 2) return true;
-    return false;
 }
 
 // One whole PT chunk on stream s: pt_every sweeps (colour passes over all
@@ -421,7 +439,7 @@ size_t qsg_workspace_bytes(const qsg_group_desc* groups, uint32_t n_groups,
     if (!groups || n_groups == 0 || !cfg || cfg->swaplog_cap == 0 || cfg->reserved) return 0;
     Layout L;
     std::string why;
-    if (!make_layout(groups, n_groups, *cfg, &L, &why)) return 0;
+    if (make_layout(groups, n_groups, *cfg, &L, &why) != QSG_OK) return 0;
     return L.total;
 }
 
@@ -437,8 +455,8 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         return fail(nullptr, QSG_E_INVALID, "workspace must be non-null and 256-byte aligned");
     Layout L;
     std::string why;
-    if (!make_layout(groups, n_groups, *cfg, &L, &why))
-        return fail(nullptr, QSG_E_INVALID, "%s", why.c_str());
+    if (qsg_status st = make_layout(groups, n_groups, *cfg, &L, &why))
+        return fail(nullptr, st, "%s", why.c_str());
     if (ws_bytes < L.total)
         return fail(nullptr, QSG_E_BUFFER, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
 
@@ -498,7 +516,7 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         g.hist = at<uint32_t>(c, gl.hist);
         c->gd.push_back(g);
         pre_sweep[i + 1] = pre_sweep[i] + g.N * qsg::sweep_blocks_per_slot(g.V);
-        pre_energy[i + 1] = pre_energy[i] + (g.N >= 2 ? g.N * qsg::energy_blocks_per_slot(g.V, qsg::kEnergyWords) : 0);
+        pre_energy[i + 1] = pre_energy[i] + g.N * qsg::energy_blocks_per_slot(g.V, qsg::kEnergyWords);
         pre_swap[i + 1] = pre_swap[i] + (g.N >= 2 ? qsg::swap_blocks(g.V) : 0);
         pre_slots[i + 1] = pre_slots[i] + g.N;
         if (g.V > max_v) max_v = g.V;
@@ -598,7 +616,7 @@ qsg_status qsg_sweep(qsg_ctx* c, uint32_t n_sweeps, uint32_t flags) {
         return fail(c, QSG_E_INVALID, "QSG_GRAPH and QSG_FUSED need QSG_BATCHED");
     if (qsg_status st = check_ready(c)) return st;
     const bool batched = flags & QSG_BATCHED;
-    const bool do_pt = !(flags & QSG_NO_PT) && c->cfg.pt_every > 0 && any_pt(c);
+    const bool do_pt = !(flags & QSG_NO_PT) && c->cfg.pt_every > 0;
     const uint32_t pe = c->cfg.pt_every;
     uint32_t done = 0;
     while (done < n_sweeps) {
@@ -653,7 +671,6 @@ qsg_status qsg_sweep(qsg_ctx* c, uint32_t n_sweeps, uint32_t flags) {
 qsg_status qsg_pt_swap(qsg_ctx* c) {
     if (qsg_status st = check_ctx(c)) return st;
     if (qsg_status st = check_ready(c)) return st;
-    if (!any_pt(c)) return QSG_OK;
     if (qsg_status st = batched_pt(c, c->stream, 0)) return st;
     QSG_HIP(c, qsg::launch_advance(c->d_counters, 0, 1, c->stream));
     c->p += 1;

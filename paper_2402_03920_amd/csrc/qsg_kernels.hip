@@ -153,10 +153,11 @@ struct SweepQueue {
     uint64_t nt0[kSweepBlock], nt2[kSweepBlock], acc[kSweepBlock], und[kSweepBlock];
 };
 
-// Spin and coupling words are addressed as base + 32-bit byte offset (a
-// slot and the coupling arrays are far below 4 GiB), so global accesses keep
-// the base in SGPRs and only the offset in a VGPR.  The fused kernel may hold
-// a slot in LDS and addresses it generically.
+// Spin and coupling words are addressed as base + 32-bit byte offset, so
+// global accesses keep the base in SGPRs and only the offset in a VGPR.  The
+// host rejects slots of more than 2^29 words, so a word index i < 2^29 gives
+// a byte offset i * 8 < 2^32.  The fused kernel may hold a slot in LDS and
+// addresses it generically.
 typedef char __attribute__((address_space(1))) GlobalByte;
 template <bool kGlobal>
 __device__ __forceinline__ uint64_t load64(const uint64_t* base, uint32_t i) {
@@ -776,7 +777,6 @@ __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
     __shared__ uint64_t s_mask[kMaxSlots];
     const uint32_t j = threadIdx.x;
     const uint32_t N = G.N;
-    if (N < 2) return;  // nothing to exchange
     const int32_t V = (int32_t)G.V;
     for (uint32_t g = 0; g < N; ++g) {
         int32_t* c = G.cnt + g * kCntStride;
@@ -809,13 +809,16 @@ __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
         const int32_t nx_sp = s_sp[g + 1][j];
         const int32_t nx_t = s_t[g + 1][j];
         const uint32_t nx_w = s_w[g + 1][j];
-        const int32_t D = G.exch_all ? (nx_sp + nx_t) - (cur_sp + cur_t) : nx_t - cur_t;
+        // |Bsp| <= 2V and |Bt| <= V with V <= 2^29: the difference of two
+        // whole energies needs 64 bits, that of two time-bond sums does not
+        const int64_t D = G.exch_all ? ((int64_t)nx_sp + nx_t) - ((int64_t)cur_sp + cur_t)
+                                     : (int64_t)(nx_t - cur_t);
         bool accept;
         const uint32_t len = __builtin_amdgcn_readlane(my_len, g);
         if (__builtin_amdgcn_readlane(my_eq, g) || D >= 0) {
             accept = true;
         } else {
-            const uint32_t m = (uint32_t)(-D) >> 2;
+            const uint32_t m = (uint32_t)((uint64_t)(-D) >> 2);
             const uint32_t th = (m >= 1 && m <= len) ? G.sw_thr[(size_t)g * G.sw_cap + (m - 1)] : 0u;
             const uint4 o = philox(make_uint4(j >> 2, p, (1u << 24) | g, G.gid), G.key0, G.key1);
             const uint32_t sel = j & 3u;
@@ -855,7 +858,10 @@ __device__ __forceinline__ void pt_group(const GroupDev& G, uint32_t p) {
     }
     if (j == 0) G.lastmask[N - 1] = any ? 1ull : 0ull;
 
-    // round trips 0 -> N-1 -> 0; this step ends at PT time p+1
+    // round trips 0 -> N-1 -> 0; this step ends at PT time p+1.  One slot
+    // has no exchange partner and no pair of distinct end slots: its walkers
+    // never move, and no round trip is counted.
+    if (N < 2) return;
     const uint32_t now = p + 1;
     RoundTrip& r0 = G.rt[s_w[0][j] * 64 + j];
     if (r0.state == 2) {

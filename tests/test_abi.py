@@ -249,3 +249,26 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
         qsg.lib()
     with pytest.raises(ImportError):
         qsg.tm_dim(3)
+
+
+def test_slot_size_limit_is_enforced_without_touching_the_device():
+    """A slot of more than 2^29 words is refused (32-bit byte offsets and
+    32-bit bond sums): qsg_workspace_bytes gives 0 and qsg_create returns
+    QSG_E_UNSUPPORTED with no context; exactly 2^29 words is accepted."""
+    at_limit = _desc(L=256, L_tau=8192, n_gamma=1)
+    assert _ws_bytes(at_limit) > (1 << 29) * 8
+    over = _desc(L=256, L_tau=16384, n_gamma=1)
+    assert _ws_bytes(over) == 0
+    arr = (qsg.qsg_group_desc * 1)(over)
+    cfg = qsg.qsg_run_config(10, 16, 0, 0)
+    out = C.c_void_p()
+    rc = qsg.lib().qsg_create(arr, 1, C.byref(cfg), C.c_void_p(4096), 1 << 40, None,
+                              C.byref(out))
+    assert rc == qsg.QSG_E_UNSUPPORTED and not out.value
+    assert b"2^29" in qsg.lib().qsg_last_error(None)
+    # groups that together need 2^31 or more blocks in one pass
+    many = (qsg.qsg_group_desc * 64)(*([_desc(L=256, L_tau=8192, n_gamma=64)] * 64))
+    assert qsg.lib().qsg_workspace_bytes(many, 64, C.byref(cfg)) == 0
+    rc = qsg.lib().qsg_create(many, 64, C.byref(cfg), C.c_void_p(4096), 1 << 62, None,
+                              C.byref(out))
+    assert rc == qsg.QSG_E_UNSUPPORTED and not out.value
