@@ -100,3 +100,19 @@ def test_adam_first_step_moves_by_lr():
     p1, m, v = mlp.adam(p, g, np.zeros(4), np.zeros(4), 1, 0.01)
     assert np.allclose(p1[:3], -0.01 * np.sign(g[:3]), rtol=1e-6)
     assert p1[3] == 0.0
+
+
+def test_gelu_is_the_exact_erf_form():
+    """GELU(x) = x Phi(x) with Phi the standard normal distribution function:
+    table values Phi(1) = 0.8413447460685429, Phi(2) = 0.9772498680518208 and
+    the density phi(1) = 0.24197072451914337.  The tanh approximation of
+    GELU is 1.5e-4 off at x = 1, the sigmoid form x sigma(1.702 x) 2e-2."""
+    phi1, Phi1, Phi2 = 0.24197072451914337, 0.8413447460685429, 0.9772498680518208
+    assert abs(mlp.gelu(1.0) - Phi1) < 1e-15
+    assert abs(mlp.gelu(-1.0) - (-(1.0 - Phi1))) < 1e-15
+    assert abs(mlp.gelu(2.0) - 2 * Phi2) < 1e-15
+    assert mlp.gelu(0.0) == 0.0
+    # derivative Phi(x) + x phi(x)
+    assert abs(mlp.gelu_grad(0.0) - 0.5) < 1e-15
+    assert abs(mlp.gelu_grad(1.0) - (Phi1 + phi1)) < 1e-15
+    assert abs(mlp.gelu_grad(-1.0) - ((1.0 - Phi1) - phi1)) < 1e-15

@@ -590,3 +590,241 @@ def test_tau_overlaps_closed_forms_and_symmetry():
     # independent random spins: <Qt^2> = L^2 away from tau = 0
     m = c["q2"][:, 1:].mean() / L_tau
     assert abs(m - L * L) < 0.1 * L * L
+
+
+# ------------------------------------------------------------------------
+# Measurements of App. A / App. E taken at every PT step: the same-time,
+# same-tau replica overlap q of lane pairs (2p, 2p+1) and the histogram of
+# unsatisfied time bonds.  Each expected value is built by hand from a
+# configuration whose answer is known, not by re-running the oracle's sums.
+
+def _pair_spins(V, even_words, relation):
+    """Words whose odd lanes are built from the even lanes: relation[p] is
+    'same' (lane 2p+1 = lane 2p) or 'flip' (lane 2p+1 = -lane 2p) for the
+    32 pairs."""
+    out = np.zeros(V, dtype=np.uint64)
+    for s in range(V):
+        w = int(even_words[s])
+        word = 0
+        for p in range(32):
+            b = (w >> (2 * p)) & 1
+            ob = b if relation[p] == "same" else 1 - b
+            word |= (b << (2 * p)) | (ob << (2 * p + 1))
+        out[s] = word
+    return out
+
+
+def test_overlap_of_identical_and_complementary_pairs():
+    """q_p = sum over sites of S^{2p} S^{2p+1} (App. E, tau1 = tau2, t1 = t2):
+    +V for identical lanes and -V for complementary ones, whatever the
+    configuration; pairing any other two lanes (say p and p+32) would give
+    values near 0 for these random words."""
+    L, L_tau = 4, 6
+    V = L * L * L_tau
+    rel = ["same" if p % 3 else "flip" for p in range(32)]
+    spins = _pair_spins(V, _random_words(V, 11), rel)
+    og = chain.OracleGroup(L, L_tau, 1.0, [1.0], 0, 42, [1] * 64, spins=spins)
+    _, _, q = og.recompute()
+    want = np.array([V if r == "same" else -V for r in rel])
+    assert np.array_equal(q[0], want)
+
+
+def test_overlap_counts_differing_sites():
+    """Pair p differs on exactly d_p chosen sites: q_p = V - 2 d_p."""
+    L, L_tau = 4, 4
+    V = L * L * L_tau
+    rng = np.random.Generator(np.random.PCG64(12))
+    base = _pair_spins(V, _random_words(V, 13), ["same"] * 32)
+    d = rng.integers(0, V + 1, size=32)
+    spins = base.copy()
+    for p in range(32):
+        for s in rng.choice(V, size=int(d[p]), replace=False):
+            spins[s] ^= np.uint64(1 << (2 * p + 1))
+    og = chain.OracleGroup(L, L_tau, 1.0, [1.0, 1.5], 0, 42, [1] * 64,
+                           spins=np.concatenate([spins, base]))
+    _, _, q = og.recompute()
+    assert np.array_equal(q[0], V - 2 * d)
+    assert np.all(q[1] == V)
+    # the PT step adds q and q^2 of the configuration before any exchange
+    og.pt_step()
+    assert np.array_equal(og.sum_q.reshape(2, 32)[0], V - 2 * d)
+    assert np.array_equal(og.sum_q2.reshape(2, 32)[0], (V - 2 * d) ** 2)
+
+
+def test_overlap_of_independent_lanes_has_variance_V():
+    """Independent uniform spins: q_p is a sum of V independent +-1, so
+    <q> = 0 and <q^2> = V."""
+    L, L_tau = 4, 8
+    V = L * L * L_tau
+    qs = []
+    for seed in range(40):
+        og = chain.OracleGroup(L, L_tau, 1.0, [1.0], 0, 42, [1] * 64,
+                               spins=_random_words(V, 100 + seed))
+        qs.append(og.recompute()[2][0])
+    q = np.concatenate(qs).astype(np.float64)
+    n = q.size
+    assert abs(q.mean()) < 5 * math.sqrt(V / n)
+    # var(q^2) = 3V^2 - 2V for sums of independent +-1
+    assert abs((q * q).mean() - V) < 5 * math.sqrt((2 * V * V - 2 * V) / n)
+
+
+def _columns_with_breaks(L, L_tau, breaks_per_lane):
+    """Configuration (one slot) in which lane j has exactly
+    breaks_per_lane[j] unsatisfied time bonds: column c of the plane flips
+    sign after slice 0 and back after slice b_c (two breaks per flipped
+    column; the count of a periodic ring is even)."""
+    P = L * L
+    words = np.zeros((L_tau, P), dtype=np.uint64)
+    for j, u in enumerate(breaks_per_lane):
+        assert u % 2 == 0 and u // 2 <= P
+        for c in range(u // 2):
+            b = 1 + (c % (L_tau - 1))
+            for t in range(1, b + 1):
+                words[t, c] |= np.uint64(1 << j)
+    return words.reshape(-1)
+
+
+def test_unsatisfied_time_bond_histogram_bins():
+    """Lane j with u_j unsatisfied time bonds is counted in bin
+    u_j * 1024 // (V + 1) of its slot at a PT step; u is counted here
+    directly from the words, bond by bond."""
+    for L, L_tau in ((2, 4), (4, 8)):
+        V = L * L * L_tau
+        rng = np.random.Generator(np.random.PCG64(V))
+        u = 2 * rng.integers(0, L * L + 1, size=64)
+        u[0], u[1] = 0, 2 * L * L  # both ends of the range
+        cfg = _columns_with_breaks(L, L_tau, u)
+        cfg2 = _random_words(V, 21)
+        og = chain.OracleGroup(L, L_tau, 1.0, [1.0, 2.0], 0, 42, [1] * 64,
+                               spins=np.concatenate([cfg, cfg2]))
+        og.pt_step()
+        h = og.hist.reshape(2, 1024)
+        for slot, words in ((0, cfg), (1, cfg2)):
+            w = words.reshape(L_tau, L * L)
+            direct = np.zeros(64, dtype=np.int64)
+            for t in range(L_tau):
+                diff = w[t] ^ w[(t + 1) % L_tau]
+                for j in range(64):
+                    direct[j] += int(sum((int(x) >> j) & 1 for x in diff))
+            if slot == 0:
+                assert np.array_equal(direct, u)
+            want = np.zeros(1024, dtype=np.int64)
+            for j in range(64):
+                want[direct[j] * 1024 // (V + 1)] += 1
+            assert np.array_equal(h[slot], want), (L, L_tau, slot)
+
+
+def test_one_slot_group_is_measured_without_exchanges():
+    """A one-slot group has no exchange partner: a PT step exchanges nothing
+    and counts no round trip, but its energies, overlaps and histogram are
+    measured like any other slot's (App. A)."""
+    og = chain.OracleGroup(4, 4, 1.0, [1.0], 0, 42, [1] * 64)
+    og.run(30, 10)
+    assert og.p == 3
+    assert np.all(og.hist.sum() == 3 * 64)
+    assert np.all(og.rt_count == 0)
+    assert np.all(og.walker == 0)
+    Bsp, Bt, q = og.recompute()
+    assert np.any(og.sum_Bt != 0) and np.any(og.sum_q2 != 0)
+
+
+# ------------------------------------------------------------------------
+# Lane numbers of the Metropolis test: bit (31 - b) of lane j's r is bit j
+# of level b, level 2q = o0 | o1 << 32 and level 2q+1 = o2 | o3 << 32 of
+# the Philox block with counter (s, t, (g << 4) | q, group_id).  The three
+# published known-answer vectors fix two levels each without running any
+# generator code.
+
+def _levels_from_kat(o):
+    return (int(o[0]) | int(o[1]) << 32, int(o[2]) | int(o[3]) << 32)
+
+
+@pytest.mark.parametrize("row", range(3))
+def test_metropolis_levels_from_published_philox_outputs(philox_kat, row):
+    ctr, key, out = philox_kat[row]
+    s, t, c2, gid = ctr
+    seed = key[0] | key[1] << 32
+    g, q = c2 >> 4, c2 & 15  # counter word 2 = (g << 4) | q in domain 0
+    lv = _levels_from_kat(out)
+    r = chain.metropolis_r(seed, gid, s, t, g)
+    for j in range(64):
+        for h in (0, 1):
+            b = 2 * q + h
+            assert (int(r[j]) >> (31 - b)) & 1 == (lv[h] >> j) & 1, (row, j, b)
+
+
+def test_pt_number_from_published_philox_output(philox_kat):
+    """PT numbers: word j & 3 of the block with counter (j >> 2, p,
+    (1 << 24) | g, group_id); the third known-answer vector has a counter
+    word 2 whose bit 24 is set, so it is the block of pair g = that word."""
+    ctr, key, out = philox_kat[2]
+    assert (ctr[2] >> 24) & 1
+    seed = key[0] | key[1] << 32
+    for w in range(4):
+        j = (ctr[0] << 2) | w
+        assert chain.pt_r(seed, ctr[3], ctr[1], ctr[2], j) == out[w]
+
+
+def test_lane_numbers_are_independent_across_lanes():
+    """Different lanes draw different numbers: over many (s, t, g) no two
+    lanes of a word share r, and every pair of lanes agrees on the top bit
+    half of the time (a level assembled from one output word twice, or a
+    lane read twice, makes two lanes equal)."""
+    rs = np.stack([chain.metropolis_r(7, 3, s, t, g)
+                   for s in range(60) for t in range(4) for g in range(2)])
+    n = rs.shape[0]
+    for row in rs:
+        assert len(set(int(x) for x in row)) == 64
+    top = (rs >> np.uint32(31)).astype(np.int64)
+    agree = (top[:, :, None] == top[:, None, :]).mean(axis=0)
+    off = agree[~np.eye(64, dtype=bool)]
+    assert np.all(np.abs(off - 0.5) < 6 * math.sqrt(0.25 / n))
+    low = (rs & np.uint32(0xFF)).astype(np.int64)
+    corr = np.corrcoef(low.T)[~np.eye(64, dtype=bool)]
+    assert np.all(np.abs(corr) < 6 / math.sqrt(n))
+
+
+# ------------------------------------------------------------------------
+# Exact quantisation thr = ceil(2^32 p) - 1, i.e. thr < 2^32 p <= thr + 1
+# (accept <=> r < 2^32 p for a uniform 32-bit r).  Checked in double where
+# 2^32 p is not within 1e-3 of an integer, so that floor, round or an
+# off-by-one each fail on a good share of the entries.
+
+def _check_quantised(thr, x):
+    frac = x - math.floor(x)
+    if 1e-3 < frac < 1 - 1e-3:
+        assert thr == math.ceil(x) - 1, (thr, x)
+        return 1
+    return 0
+
+
+@pytest.mark.parametrize("beta,L_tau,lo,hi,n", [(8.0, 128, 2.0, 4.0, 32), (4.0, 32, 1.5, 4.5, 16),
+                                               (128.0, 2048, 2.8, 3.6, 48), (1.0, 8, 0.2, 0.9, 6)])
+def test_metropolis_thresholds_are_ceil_of_scaled_probability(beta, L_tau, lo, hi, n):
+    lad = W.geometric_ladder(lo, hi, n)
+    thr = tables.metropolis_thresholds(beta, L_tau, lad)
+    k = beta / L_tau
+    checked = 0
+    for g, G in enumerate(lad):
+        kp = -0.5 * math.log(math.tanh(beta * G / L_tau))
+        for ns in range(5):
+            for nt in range(3):
+                dE = 4 * k * (2 - ns) + 4 * kp * (1 - nt)
+                if dE <= 0:
+                    assert int(thr[g, ns, nt]) == U32 - 1
+                    continue
+                checked += _check_quantised(int(thr[g, ns, nt]), U32 * math.exp(-dE))
+    assert checked >= 4 * n
+
+
+def test_exchange_thresholds_are_ceil_of_scaled_probability():
+    beta, L_tau = 16.0, 256
+    lad = W.geometric_ladder(2.0, 4.0, 12)
+    eq, ln, tabs = tables.swap_tables(beta, L_tau, lad)
+    checked = 0
+    for g in range(len(lad) - 1):
+        d = (-0.5 * math.log(math.tanh(beta * lad[g] / L_tau))
+             + 0.5 * math.log(math.tanh(beta * lad[g + 1] / L_tau)))
+        for m in range(1, int(ln[g]) + 1, 7):
+            checked += _check_quantised(int(tabs[g][m - 1]), U32 * math.exp(-4 * m * d))
+    assert checked > 100
