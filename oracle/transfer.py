@@ -20,11 +20,18 @@ is the sum over the 2 L^2 bonds (site, +x) and (site, +y) of J S S'
 
 The parity P = prod_j sigma^X_j commutes with T.  With n an (L^2 - 1)-bit
 index (the last site's spin fixed to +1), the sector bases are
-|n>_e,o = (|n> +- |~n>) / sqrt(2), ~n the complement of all L^2 bits.  On
-them W acts as on |n>, sigma^X_j (j < L^2 - 1) maps n to n ^ 2^j, and the
-last site's sigma^X maps n to +-(its complement in L^2 - 1 bits), the sign
-being the sector's.  `apply` is that product, written in the paper's order:
-W, the rounds j = 0 .. L^2 - 2, the last site's round, W.
+|n>_e,o = (|n> +- |~n>) / sqrt(2), ~n the complement of all L^2 bits.  From
+the matrix elements above, <m|B|n> = prod_{j < L^2-1} F[m_j][n_j] times jp
+(the last site agrees) and <m|B|~n> = prod_{j < L^2-1} F[m_j][1-n_j] times
+jm, with F = [[jp, jm], [jm, jp]], so in a sector of parity s
+
+    B_s = F (x) F (x) ... (x) F  (jp 1 + s jm C),
+
+a Kronecker product of L^2 - 1 copies of F times a term in C, the map
+n -> complement of n in L^2 - 1 bits.  `apply` evaluates T x = W B_s W x
+in that form: x times W viewed as a tensor with one axis of length 2 per
+bit, F contracted with every axis (tensordot), the C term as the reversed
+vector (complementing every bit of an index i gives N - 1 - i), W again.
 """
 from __future__ import annotations
 
@@ -80,13 +87,13 @@ def apply(L: int, k: float, kp: float, jx, jy, parity: int, x: np.ndarray,
     if w is None:
         w = weights(L, k, jx, jy)
     jp, jm = couplings(kp)
-    idx = np.arange(N, dtype=np.int64)
-    psi = w * x                                       # initialisation: W
-    for j in range(n):                                # rounds: sigma^X_j, j < L^2 - 1
-        psi = jp * psi + jm * psi[idx ^ (1 << j)]
-    comp = (N - 1) - idx                              # last site: complement of n bits
-    psi = jp * psi + parity * jm * psi[comp]
-    return w * psi                                    # finalisation: W
+    F = np.array([[jp, jm], [jm, jp]])
+    t = (w * x).reshape((2,) * n)
+    for axis in range(n):  # F on every bit (F is symmetric, the order is free)
+        t = np.moveaxis(np.tensordot(F, t, axes=([1], [axis])), 0, axis)
+    y = t.reshape(N)
+    y = jp * y + parity * jm * y[::-1]
+    return w * y
 
 
 def sector_matrix(L: int, k: float, kp: float, jx, jy, parity: int) -> np.ndarray:
