@@ -1,14 +1,18 @@
 """Benchmark of the MCQSG Metropolis + parallel-tempering hot path on one GPU.
 
-Workload: 64 disorder samples (one group of 64 replicas each), L=16,
-L_tau=128, beta=8, 32 Gammas geometric in [2, 4], PT every 10 sweeps; seeded
-synthetic couplings and spins.  A step is one PT chunk over every sample:
-10 sweeps (red + blue pass each), the energy/overlap pass, the PT step and
-the exchange pass.
+Default workload: the batched uneven ensemble, 256 disorder samples (one
+group of 64 replicas each) with L in {8,12,16,20,24}, L_tau in
+{64,128,256}, beta = L_tau/16 and 24-48 Gammas geometric in [2, 4], PT
+every 10 sweeps; seeded synthetic couplings and spins.  A step is one PT
+chunk over every sample: 10 sweeps (red + blue pass each), the
+energy/overlap pass, the PT step and the exchange pass.
 
 Prints one JSON line.  value = picoseconds per spin-update of the batched
 path (one launch per pass over all samples, replayed as a HIP graph);
-plain_ps_per_spin_update is the same work launched per sample.
+plain_ps_per_spin_update is the same work launched per sample.  The other
+half of the metric, PT round trips per hour with the learned against the
+geometric ladder, is measured by `python -m paper_2402_03920_amd.learn_ladder`
+(profiles/ladder_eval_results.txt); the line quotes that record.
 """
 from __future__ import annotations
 
@@ -43,12 +47,18 @@ def required_blocks_per_word(lanes: int = 64) -> float:
     return sum(1.0 - (1.0 - 4.0 ** (-(k - 1))) ** lanes for k in range(1, 17))
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_plain_large_traffic.txt")
 KERNEL_SOURCES = ("paper_2402_03920_amd/csrc/qsg_kernels.hip",
                   "paper_2402_03920_amd/csrc/qsg_internal.h")
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of the colour pass,
+# per workload
+TRAFFIC_FILES = {w: os.path.join(ROOT, "profiles", f"sweep_{w.replace('-', '_')}_traffic.txt")
+                 for w in ("uneven", "plain-large", "production")}
 TM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "transfer_l5_traffic.txt")
 TM_SOURCES = ("paper_2402_03920_amd/csrc/qsg_transfer.hip",
               "paper_2402_03920_amd/csrc/qsg_transfer.h")
+TRAFFIC_RECORDS = [(f, KERNEL_SOURCES) for f in TRAFFIC_FILES.values()] + \
+    [(TM_TRAFFIC_FILE, TM_SOURCES)]
+LADDER_RECORD = os.path.join(ROOT, "profiles", "ladder_eval_results.txt")
 
 
 def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
@@ -77,14 +87,43 @@ def traffic_record(path: str, sources):
     return vals
 
 
+def workload_traffic_record(workload: str):
+    """The colour pass's committed traffic and counter summary for this
+    workload, or None (none committed, or taken on other kernel sources)."""
+    path = TRAFFIC_FILES.get(workload)
+    return traffic_record(path, KERNEL_SOURCES) if path else None
+
+
 def measured_traffic(workload: str):
     """HBM bytes per launch of the colour pass on the bench workload, or
-    None (another workload, or a summary of other kernel sources)."""
-    vals = traffic_record(TRAFFIC_FILE, KERNEL_SOURCES) if workload == "plain-large" else None
+    None (no current summary for this workload)."""
+    vals = workload_traffic_record(workload)
     try:
         return int(vals["fetch_bytes_per_launch"]) + int(vals["write_bytes_per_launch"])
     except (TypeError, KeyError, ValueError):
         return None
+
+
+def ladder_record():
+    """Round trips per hour, learned against geometric ladder, from the
+    committed evaluation record (not measured by this run)."""
+    if not os.path.exists(LADDER_RECORD):
+        return None
+    out = {"source": os.path.relpath(LADDER_RECORD, ROOT),
+           "command": "python -m paper_2402_03920_amd.learn_ladder"}
+    section = None
+    with open(LADDER_RECORD) as f:
+        for line in f:
+            if line.startswith("# full evaluation"):
+                section = "full"
+            elif line.startswith("# focused"):
+                section = "focused"
+            elif section and line.startswith("round trips per hour"):
+                v = line.split(")")[-1].split()
+                out[section] = {"geometric": float(v[0]), "learned": float(v[1])}
+            elif section and line.startswith("paired round-trip gain"):
+                out[section]["paired_gain_per_sample"] = line.split(":", 1)[1].strip()
+    return out
 
 
 def parse():
@@ -94,12 +133,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--samples", type=int, default=64)
-    ap.add_argument("--workload", default="plain-large",
+    ap.add_argument("--workload", default="uneven",
                     choices=["plain-small", "plain-large", "uneven", "production", "k-ladder"],
-                    help="plain-large (default): 64 samples, L=16, L_tau=128, 32 Gammas; "
-                         "plain-small: one sample, L=8, L_tau=32; uneven: 256 samples of mixed "
-                         "shapes; production: L=24, L_tau=2048, 128 samples; k-ladder: the "
-                         "plain-large shape with the paper's coupling ladder (PT over k)")
+                    help="uneven (default): 256 samples of mixed shapes, batched against "
+                         "per-sample launches; plain-large: 64 samples, L=16, L_tau=128, "
+                         "32 Gammas; plain-small: one sample, L=8, L_tau=32; production: L=24, "
+                         "L_tau=2048, 128 samples; k-ladder: the plain-large shape with the "
+                         "paper's coupling ladder (PT over k)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default colour-pass schedule instead of tuning it per shape")
@@ -269,7 +309,7 @@ def main():
     if traffic is not None:
         result["roofline"]["hbm_GBps_measured"] = round(traffic / pass_s / 1e9, 2)
         result["roofline"]["hbm_frac_measured"] = round(traffic / pass_s / 8e12, 4)
-        rec = traffic_record(TRAFFIC_FILE, KERNEL_SOURCES)
+        rec = workload_traffic_record(args.workload)
         try:  # every VALU instruction the kernel issues (counters), not only the required ones
             executed = float(rec["valu_instr_per_wave"]) * float(rec["waves_per_launch"]) * 64
             result["roofline"]["executed_valu_frac"] = round(executed / pass_s / 1e12 / PEAK_VALU_TOPS, 4)
@@ -278,6 +318,7 @@ def main():
     result["philox_ceiling"] = dict(ceiling, sweep_required_blocks_per_s=required_rate,
                                     sweep_frac_of_ceiling=round(required_rate / ceiling["blocks_per_s"], 4))
     result["physics"] = physics
+    result["pt_roundtrips_per_hour"] = ladder_record()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps)
     print(json.dumps(result), flush=True)
