@@ -1,0 +1,98 @@
+"""GPU parity at the workloads' real shapes against stored oracle records.
+
+The oracle needs minutes for these runs (a production group of 48 slots of
+24 x 24 x 2048 words through a PT step; uneven-ensemble samples of
+L_tau = 256), so tests/golden/make_oracle_records.py ran it once and stored
+every field of the final state as digests (tests/parity_util.py): spins
+slot by slot, bond sums, walkers, round-trip trackers, per-step sums and
+histograms, acceptance counts and swap masks in full.  Here the GPU runs the
+same inputs in the batched, graph-replayed launch configuration that
+bench.py times, and its record must equal the oracle's field by field.
+"""
+import json
+import os
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import qsg_workloads as W
+from tests.parity_util import compare_records, gpu_record
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU-only hosts, never run there
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2402_03920_amd import qsg  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RECORDS = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_records.json")))
+GRAPH = qsg.QSG_BATCHED | qsg.QSG_GRAPH
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_production_group_through_a_pt_step():
+    """Both production groups (128 samples in the lanes, 48 Gammas), 10
+    sweeps and the PT step as one replayed chunk graph; group 0 against the
+    oracle: every slot's spins, the energies entering the exchange, all 47
+    pairs' decisions, walkers and round-trip trackers."""
+    wl = W.production()
+    want = RECORDS["production_g0"]
+    say("[golden] production, 2 groups x 48 slots, 10 sweeps + PT (graph)")
+    with qsg.Ensemble(wl.groups, pt_every=10, swaplog_cap=16) as ens:
+        ens.init_spins()
+        ens.sweep(10, GRAPH)
+        got = gpu_record(ens, 0)
+    compare_records(got, want, "production group 0")
+    assert sum(want["acc"]) > 0  # the step exchanged configurations
+
+
+@pytest.mark.parametrize("form", ["per-pass", "fused"])
+def test_uneven_ensemble_samples(form):
+    """All 256 uneven samples in one launch per pass (graph replay), 20
+    sweeps with PT every 10, a few groups on other colour-pass schedules;
+    samples 17 (L=20, L_tau=256), 82 (L=24, L_tau=256) and 16 (L=20,
+    L_tau=64) against the oracle."""
+    wl = W.uneven_ensemble()
+    flags = GRAPH | (qsg.QSG_FUSED if form == "fused" else 0)
+    say(f"[golden] uneven ensemble, 256 samples, 20 sweeps, form={form}")
+    with qsg.Ensemble(wl.groups, pt_every=10, swaplog_cap=16) as ens:
+        for gi, split, tile in ((17, 2, 2), (82, 6, 32), (100, 16, 4)):
+            ens.set_schedule(gi, split, tile)
+        ens.init_spins()
+        ens.sweep(20, flags)
+        cache = {}
+        for i in (17, 82, 16):
+            want = RECORDS[f"uneven_{i}"]
+            assert (want["L"], want["L_tau"], want["n_gamma"]) == \
+                (wl.groups[i].L, wl.groups[i].L_tau, wl.groups[i].n_gamma)
+            compare_records(gpu_record(ens, i, cache), want, f"uneven sample {i}")
+
+
+def test_learned_ladder_samples():
+    """Learned-ladder evaluation samples 0 and 3 on the non-geometric
+    ladders the oracle MLP decodes for them (stored as exact doubles), next
+    to two samples on the geometric ladder, 20 sweeps with PT every 10."""
+    ev = W.ladder_eval()
+    groups = list(ev.groups[:4])
+    for i in (0, 3):
+        lad = np.array([float.fromhex(h) for h in RECORDS[f"ladder_eval_learned_{i}"]["ladder_hex"]])
+        geo = W.geometric_ladder(2.0, 4.0, 32)
+        assert lad[0] == geo[0] and lad[-1] == geo[-1] and np.all(np.diff(lad) > 0)
+        assert np.max(np.abs(np.log(lad) - np.log(geo))) > 1e-3  # not the geometric ladder
+        groups[i] = replace(groups[i], gammas=lad)
+    say("[golden] learned ladders, 4 samples, 20 sweeps")
+    with qsg.Ensemble(groups, pt_every=10, swaplog_cap=16) as ens:
+        ens.init_spins()
+        ens.sweep(20, GRAPH)
+        cache = {}
+        for i in (0, 3):
+            compare_records(gpu_record(ens, i, cache), RECORDS[f"ladder_eval_learned_{i}"],
+                            f"learned-ladder sample {i}")
