@@ -111,7 +111,11 @@ typedef struct {
                              word goes through before the words still undecided
                              are packed into fewer waves (1..16; 16 = never;
                              0 = default 4).  Results do not depend on it.     */
-    uint32_t reserved;    /* must be 0 */
+    uint32_t tau_tile;    /* schedule of the colour pass: tau planes a thread
+                             walks along one column (it updates tau_tile/2 words;
+                             0 = default 8).  Each group uses the largest power
+                             of two <= tau_tile (2..32) dividing its L_tau.
+                             Results do not depend on it.                      */
 } qsg_run_config;
 
 /* qsg_sweep flags */
@@ -292,6 +296,15 @@ qsg_status qsg_build_tables_k(uint32_t n_gamma, const double* k, uint32_t cap, u
  * packed into fewer waves, 1..16 (16 = never).  Results do not depend on
  * it.  Synchronises; QSG_E_INVALID outside 1..16 (nothing changed). */
 qsg_status qsg_set_schedule(qsg_ctx* ctx, uint32_t group, uint32_t sweep_split);
+
+/* Both colour-pass knobs of one group: sweep_split as above and tau_tile,
+ * the tau planes one thread walks along its column (2..32; the group uses
+ * the largest power of two <= tau_tile that divides its L_tau).  The batched
+ * launch plan is rebuilt (and a captured graph dropped).  Results do not
+ * depend on either knob.  Synchronises; QSG_E_INVALID for values outside
+ * their ranges (nothing changed). */
+qsg_status qsg_set_colour_schedule(qsg_ctx* ctx, uint32_t group, uint32_t sweep_split,
+                                   uint32_t tau_tile);
 
 /* Wall-clock deadline checked between PT chunks of qsg_sweep (Sec. 3: the
  * MAXTIME value that stops a run cleanly before a batch limit): seconds

@@ -149,10 +149,12 @@ qsg_status make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config
         L.g.push_back(g);
     }
     // the colour pass's block map, when the groups' block counts differ
+    // (sized for the shallowest column walk, which needs the most blocks, so
+    // that any schedule set later fits)
     std::vector<uint64_t> blocks(n);
     for (uint32_t i = 0; i < n; ++i)
         blocks[i] = (uint64_t)d[i].n_gamma *
-                    qsg::sweep_blocks_per_slot(d[i].L * d[i].L * d[i].L_tau);
+                    qsg::sweep_blocks_per_slot(d[i].L * d[i].L * d[i].L_tau, 2);
     bool equal = true;
     uint64_t total_blocks = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -164,7 +166,8 @@ qsg_status make_layout(const qsg_group_desc* d, uint32_t n, const qsg_run_config
     uint64_t energy_blocks = 0, swap_blocks = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const uint32_t V = d[i].L * d[i].L * d[i].L_tau;
-        energy_blocks += (uint64_t)d[i].n_gamma * qsg::energy_blocks_per_slot(V, qsg::kEnergyWords);
+        energy_blocks += (uint64_t)d[i].n_gamma *
+                         qsg::energy_blocks_per_slot(V, qsg::tile_for(d[i].L_tau, qsg::kEnergyWords));
         swap_blocks += qsg::swap_blocks(V);
     }
     if (total_blocks >= (1ull << 31) || energy_blocks >= (1ull << 31) ||
@@ -370,6 +373,39 @@ qsg_status build_chunk_graph(qsg_ctx* c, bool fused) {
     return QSG_OK;
 }
 
+// The colour pass's batched plan from the groups' current schedules: block
+// prefix sums (uploaded), the per-group block count when all groups have
+// the same, else the block map (uploaded; its region is sized for the
+// schedule that needs the most blocks).  Synchronises the stream.
+qsg_status upload_sweep_plan(qsg_ctx* c) {
+    const uint32_t n = (uint32_t)c->gd.size();
+    std::vector<uint32_t> pre(n + 1, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        const GroupDev& g = c->gd[i];
+        pre[i + 1] = pre[i] + g.N * qsg::sweep_blocks_per_slot(g.V, g.tile);
+    }
+    hipStream_t s = c->stream;
+    qsg::BatchPlan p = qsg::make_plan(c->d_groups, at<uint32_t>(c, c->layout.prefix_sweep),
+                                      pre.data(), n, c->gd.data());
+    QSG_HIP(c, hipMemcpyAsync(const_cast<uint32_t*>(p.prefix), pre.data(), 4 * (n + 1),
+                              hipMemcpyHostToDevice, s));
+    std::vector<qsg::BlockEntry> map;
+    if (!p.per_group && c->layout.block_map.bytes) {
+        map.reserve(pre[n]);
+        for (uint32_t i = 0; i < n; ++i)
+            for (uint32_t b = 0; b < pre[i + 1] - pre[i]; ++b) map.push_back({i, b});
+        if (map.size() * sizeof(qsg::BlockEntry) > c->layout.block_map.bytes)
+            return fail(c, QSG_E_INVALID, "block map of %zu entries exceeds its region", map.size());
+        auto* d_map = at<qsg::BlockEntry>(c, c->layout.block_map);
+        QSG_HIP(c, hipMemcpyAsync(d_map, map.data(), map.size() * sizeof(qsg::BlockEntry),
+                                  hipMemcpyHostToDevice, s));
+        p.block_map = d_map;
+    }
+    QSG_HIP(c, hipStreamSynchronize(s));  // the staging vectors go out of scope
+    c->plan_sweep = p;
+    return QSG_OK;
+}
+
 }  // namespace
 
 // Checkpoint: header, then per group the device regions that carry state.
@@ -436,7 +472,9 @@ extern "C" {
 
 size_t qsg_workspace_bytes(const qsg_group_desc* groups, uint32_t n_groups,
                            const qsg_run_config* cfg) {
-    if (!groups || n_groups == 0 || !cfg || cfg->swaplog_cap == 0 || cfg->reserved) return 0;
+    if (!groups || n_groups == 0 || !cfg || cfg->swaplog_cap == 0 ||
+        cfg->tau_tile > qsg::kMaxTile || cfg->tau_tile == 1)
+        return 0;
     Layout L;
     std::string why;
     if (make_layout(groups, n_groups, *cfg, &L, &why) != QSG_OK) return 0;
@@ -450,7 +488,9 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
     if (!groups || n_groups == 0 || !cfg)
         return fail(nullptr, QSG_E_INVALID, "groups/cfg null or n_groups == 0");
     if (cfg->swaplog_cap == 0) return fail(nullptr, QSG_E_INVALID, "swaplog_cap must be >= 1");
-    if (cfg->reserved) return fail(nullptr, QSG_E_INVALID, "run config reserved field must be 0");
+    if (cfg->tau_tile > qsg::kMaxTile || cfg->tau_tile == 1)
+        return fail(nullptr, QSG_E_INVALID, "tau_tile %u outside 2..%u (0: default)", cfg->tau_tile,
+                    qsg::kMaxTile);
     if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0)
         return fail(nullptr, QSG_E_INVALID, "workspace must be non-null and 256-byte aligned");
     Layout L;
@@ -472,7 +512,7 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
     c->d_counters = at<uint32_t>(c, L.counters);
     c->d_groups = at<GroupDev>(c, L.groups_dev);
 
-    std::vector<uint32_t> pre_sweep(n_groups + 1, 0), pre_energy(n_groups + 1, 0),
+    std::vector<uint32_t> pre_energy(n_groups + 1, 0),
         pre_swap(n_groups + 1, 0), pre_slots(n_groups + 1, 0);
     uint32_t max_v = 0;
     for (uint32_t i = 0; i < n_groups; ++i) {
@@ -490,7 +530,9 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         g.div_half_row = qsg::make_divisor(d.L / 2);
         g.div_plane = qsg::make_divisor(d.L * d.L);
         g.div_row = qsg::make_divisor(d.L);
-        g.div_blocks = qsg::make_divisor(qsg::sweep_blocks_per_slot(g.V));
+        g.tile = qsg::tile_for(d.L_tau, cfg->tau_tile ? cfg->tau_tile : qsg::kDefaultTile);
+        g.etile = qsg::tile_for(d.L_tau, qsg::kEnergyWords);
+        g.div_blocks = qsg::make_divisor(qsg::sweep_blocks_per_slot(g.V, g.tile));
         g.sw_cap = swap_cap_of(d);
         g.log_cap = cfg->swaplog_cap;
         g.q_split = cfg->sweep_split ? (cfg->sweep_split > 16 ? 16 : cfg->sweep_split) : 4;
@@ -515,14 +557,11 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
         g.lastmask = at<uint64_t>(c, gl.lastmask);
         g.hist = at<uint32_t>(c, gl.hist);
         c->gd.push_back(g);
-        pre_sweep[i + 1] = pre_sweep[i] + g.N * qsg::sweep_blocks_per_slot(g.V);
-        pre_energy[i + 1] = pre_energy[i] + g.N * qsg::energy_blocks_per_slot(g.V, qsg::kEnergyWords);
+        pre_energy[i + 1] = pre_energy[i] + g.N * qsg::energy_blocks_per_slot(g.V, g.etile);
         pre_swap[i + 1] = pre_swap[i] + (g.N >= 2 ? qsg::swap_blocks(g.V) : 0);
         pre_slots[i + 1] = pre_slots[i] + g.N;
         if (g.V > max_v) max_v = g.V;
     }
-    c->plan_sweep = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_sweep), pre_sweep.data(),
-                                   n_groups, c->gd.data());
     c->plan_energy = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_energy),
                                     pre_energy.data(), n_groups, c->gd.data());
     c->plan_swap = qsg::make_plan(c->d_groups, at<uint32_t>(c, L.prefix_swap), pre_swap.data(),
@@ -548,29 +587,13 @@ qsg_status qsg_create(const qsg_group_desc* groups, uint32_t n_groups, const qsg
     CREATE_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
     CREATE_HIP(hipMemcpyAsync(c->d_groups, c->gd.data(), sizeof(GroupDev) * n_groups,
                               hipMemcpyHostToDevice, s));
-    CREATE_HIP(hipMemcpyAsync(const_cast<uint32_t*>(c->plan_sweep.prefix), pre_sweep.data(), 4 * (n_groups + 1),
-                              hipMemcpyHostToDevice, s));
     CREATE_HIP(hipMemcpyAsync(const_cast<uint32_t*>(c->plan_energy.prefix), pre_energy.data(), 4 * (n_groups + 1),
                               hipMemcpyHostToDevice, s));
     CREATE_HIP(hipMemcpyAsync(const_cast<uint32_t*>(c->plan_swap.prefix), pre_swap.data(), 4 * (n_groups + 1),
                               hipMemcpyHostToDevice, s));
     CREATE_HIP(hipMemcpyAsync(const_cast<uint32_t*>(c->plan_slots.prefix), pre_slots.data(),
                               4 * (n_groups + 1), hipMemcpyHostToDevice, s));
-    std::vector<qsg::BlockEntry> block_map;
-    if (L.block_map.bytes) {
-        block_map.reserve(pre_sweep[n_groups]);
-        for (uint32_t i = 0; i < n_groups; ++i)
-            for (uint32_t b = 0; b < pre_sweep[i + 1] - pre_sweep[i]; ++b) block_map.push_back({i, b});
-        if (block_map.size() * sizeof(qsg::BlockEntry) != L.block_map.bytes) {
-            fail(c, QSG_E_INVALID, "block map of %zu entries does not fill its region",
-                 block_map.size());
-            return bail(QSG_E_INVALID);
-        }
-        auto* d_map = at<qsg::BlockEntry>(c, L.block_map);
-        CREATE_HIP(hipMemcpyAsync(d_map, block_map.data(), L.block_map.bytes,
-                                  hipMemcpyHostToDevice, s));
-        c->plan_sweep.block_map = d_map;
-    }
+    if (qsg_status st = upload_sweep_plan(c)) return bail(st);
     const uint32_t zero2[2] = {0, 0};
     CREATE_HIP(hipMemcpyAsync(c->d_counters, zero2, sizeof zero2, hipMemcpyHostToDevice, s));
     for (uint32_t i = 0; i < n_groups; ++i) {
@@ -925,26 +948,43 @@ qsg_status qsg_build_tables_k(uint32_t n_gamma, const double* k, uint32_t cap, u
 // qsg::same_but_identity lists every field of the group record and the
 // kernels' group_record moves every pointer: a new field must be added to
 // both.
-static_assert(sizeof(GroupDev) == 12 * 4 + 5 * sizeof(qsg::Divisor) + 18 * sizeof(void*),
+static_assert(sizeof(GroupDev) == 14 * 4 + 5 * sizeof(qsg::Divisor) + 18 * sizeof(void*),
               "GroupDev changed: update same_but_identity and group_record");
 
-qsg_status qsg_set_schedule(qsg_ctx* c, uint32_t group, uint32_t sweep_split) {
+qsg_status qsg_set_colour_schedule(qsg_ctx* c, uint32_t group, uint32_t sweep_split,
+                                   uint32_t tau_tile) {
     if (qsg_status st = check_ctx(c)) return st;
     if (group >= c->gd.size()) return fail(c, QSG_E_INVALID, "group %u out of range", group);
     if (sweep_split < 1 || sweep_split > 16)
         return fail(c, QSG_E_INVALID, "sweep_split %u outside 1..16", sweep_split);
+    if (tau_tile < 2 || tau_tile > qsg::kMaxTile)
+        return fail(c, QSG_E_INVALID, "tau_tile %u outside 2..%u", tau_tile, qsg::kMaxTile);
     GroupDev& g = c->gd[group];
+    const GroupDev before = g;
     g.q_split = sweep_split;
+    g.tile = qsg::tile_for(g.Ltau, tau_tile);
+    g.div_blocks = qsg::make_divisor(qsg::sweep_blocks_per_slot(g.V, g.tile));
     // later launches (and the next graph capture) see the new record, in
     // device memory and in the plans' copies
-    QSG_HIP(c, hipMemcpyAsync(c->d_groups + group, &g, sizeof(GroupDev), hipMemcpyHostToDevice,
-                              c->stream));
-    QSG_HIP(c, hipStreamSynchronize(c->stream));
+    hipError_t e = hipMemcpyAsync(c->d_groups + group, &g, sizeof(GroupDev),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        g = before;
+        return fail(c, QSG_E_DEVICE, "schedule upload: %s", hipGetErrorString(e));
+    }
     const uint32_t n = (uint32_t)c->gd.size();
-    for (qsg::BatchPlan* p : {&c->plan_sweep, &c->plan_energy, &c->plan_swap, &c->plan_slots})
+    if (qsg_status st = upload_sweep_plan(c)) return st;
+    for (qsg::BatchPlan* p : {&c->plan_energy, &c->plan_swap, &c->plan_slots})
         qsg::set_plan_shape(*p, c->gd.data(), n);
     destroy_graph(c);
     return QSG_OK;
+}
+
+qsg_status qsg_set_schedule(qsg_ctx* c, uint32_t group, uint32_t sweep_split) {
+    if (qsg_status st = check_ctx(c)) return st;
+    if (group >= c->gd.size()) return fail(c, QSG_E_INVALID, "group %u out of range", group);
+    return qsg_set_colour_schedule(c, group, sweep_split, c->gd[group].tile);
 }
 
 qsg_status qsg_set_deadline(qsg_ctx* c, double seconds_from_now) {

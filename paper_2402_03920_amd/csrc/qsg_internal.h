@@ -63,10 +63,12 @@ struct GroupDev {
     uint32_t sw_cap;      // entries per exchange table
     uint32_t log_cap;     // rows of the swap log
     uint32_t q_split;     // colour-pass schedule: Philox blocks before packing
+    uint32_t tile;        // colour-pass schedule: tau planes per column walk (even, divides Ltau)
     uint32_t exch_all;    // PT energy: 0 time bonds (Gamma ladder), 1 all bonds (k ladder)
     uint32_t anti;        // 1: antiperiodic along tau (the wrapping time bond flips sign)
+    uint32_t etile;       // energy pass, batched: tau planes per column walk (divides Ltau)
     Divisor div_half_plane, div_half_row, div_plane, div_row;
-    Divisor div_blocks;   // colour-pass blocks per slot
+    Divisor div_blocks;   // colour-pass blocks per slot (sweep_blocks_per_slot(V, tile))
     uint64_t* spins;          // [N][Ltau][L][L]
     uint64_t* Jx;             // [L*L]
     uint64_t* Jy;             // [L*L]
@@ -146,7 +148,8 @@ inline bool same_but_identity(const GroupDev& a, const GroupDev& b, uint64_t shi
     };
     auto div = [](Divisor x, Divisor y) { return x.m == y.m && x.s == y.s; };
     return a.L == b.L && a.Ltau == b.Ltau && a.N == b.N && a.V == b.V && a.sw_cap == b.sw_cap &&
-           a.log_cap == b.log_cap && a.q_split == b.q_split && a.exch_all == b.exch_all &&
+           a.log_cap == b.log_cap && a.q_split == b.q_split && a.tile == b.tile &&
+           a.exch_all == b.exch_all && a.etile == b.etile &&
            a.anti == b.anti && div(a.div_half_plane, b.div_half_plane) &&
            div(a.div_half_row, b.div_half_row) && div(a.div_plane, b.div_plane) &&
            div(a.div_row, b.div_row) && div(a.div_blocks, b.div_blocks) &&
@@ -202,32 +205,49 @@ hipError_t launch_energy_batched(const BatchPlan& plan, hipStream_t s);
 hipError_t launch_chunk_fused(const BatchPlan& slots, const uint32_t* ctr, uint32_t n_sweeps,
                               uint32_t lds_words, hipStream_t s);
 constexpr uint32_t kFusedLdsMaxWords = 7168;  // 56 KiB of spins per block
+// Column-walk depth of the colour pass: the default and the largest allowed
+// (tau planes per thread; each thread updates tile/2 words).
+constexpr uint32_t kDefaultTile = 8;
+constexpr uint32_t kMaxTile = 32;
+// Largest power of two <= cap that divides Ltau (Ltau is even: at least 2).
+inline uint32_t tile_for(uint32_t Ltau, uint32_t cap) {
+    uint32_t t = 2;
+    while (t * 2 <= cap && Ltau % (t * 2) == 0) t *= 2;
+    return t;
+}
 hipError_t launch_pt_batched(const GroupDev* groups, uint32_t n_groups, const uint32_t* ctr,
                              uint32_t p_add, hipStream_t s);
 hipError_t launch_swap_apply_batched(const BatchPlan& plan, hipStream_t s);
 
 // Blocks one group needs in each pass (host and device agree on these).
-__host__ __device__ inline uint32_t sweep_blocks_per_slot(uint32_t V);
+// The colour pass gives each thread one column (x, y) of one tau tile of
+// `tile` planes: V / tile threads per slot.
+__host__ __device__ inline uint32_t sweep_blocks_per_slot(uint32_t V, uint32_t tile);
 __host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V, uint32_t words);
 __host__ __device__ inline uint32_t swap_blocks(uint32_t V);
 
 constexpr uint32_t kMaxSlots = 64;  // slots per group (the C ABI's QSG_MAX_GAMMA)
 constexpr int kSweepBlock = 256;   // threads per block of a colour pass
 constexpr uint32_t kWaveSize = 64;
-constexpr int kEnergyWords = 64;   // words per thread, batched energy pass
-constexpr int kEnergyWordsSlot = 32;  // words per thread, energy pass of one group
+// Energy pass: each thread walks one column through a tau tile of at most
+// this many planes (batched launches; a launch for one group takes at most
+// kEnergyPlanesSlot so that it still has enough blocks).
+constexpr int kEnergyWords = 64;
+constexpr int kEnergyPlanesSlot = 16;
 constexpr int kEnergyBlock = 256;
 constexpr int kSwapBlock = 256;
 
 }  // namespace qsg
 
 namespace qsg {
-__host__ __device__ inline uint32_t sweep_blocks_per_slot(uint32_t V) {
-    return (V / 2 + kSweepBlock - 1) / kSweepBlock;
+__host__ __device__ inline uint32_t sweep_blocks_per_slot(uint32_t V, uint32_t tile) {
+    return (V / tile + kSweepBlock - 1) / kSweepBlock;
 }
-__host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V, uint32_t words) {
-    const uint32_t per_block = kEnergyBlock * words;
-    return (V + per_block - 1) / per_block;
+// The fused chunk kernel walks a slot's colour-c words block by block.
+__host__ __device__ inline uint32_t fused_words_per_colour(uint32_t V) { return V / 2; }
+// `planes` divides Ltau, so V / planes threads cover the slot exactly.
+__host__ __device__ inline uint32_t energy_blocks_per_slot(uint32_t V, uint32_t planes) {
+    return (V / planes + kEnergyBlock - 1) / kEnergyBlock;
 }
 __host__ __device__ inline uint32_t swap_blocks(uint32_t V) {
     return (V + kSwapBlock - 1) / kSwapBlock;

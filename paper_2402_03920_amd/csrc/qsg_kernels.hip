@@ -140,17 +140,24 @@ struct WordState {
     uint64_t acc, und;
 };
 
-// Words of one block still undecided after the first levels wait in LDS
-// (structure of arrays) and are finished by as few waves as possible.  The
-// n_t = 1 plane is not stored: the three n_t planes are one-hot.
-// Two pairs of counters alternate between consecutive calls of a block: a
-// slow thread may still be reading the previous call's count after a fast
-// one has cleared the counters for the next call.
+// LDS of a colour-pass block.  At the start of a call every thread writes
+// its word's site, centre word and class planes to its own slot (the n_t = 1
+// plane is not stored: the three n_t planes are one-hot), so they need not
+// stay in registers through the comparison.  Words still undecided after
+// the first levels are queued as (owner thread, accepted, undecided lanes)
+// and finished by as few waves as possible, reading the rest from the
+// owner's slot.  Two pairs of counters alternate between consecutive calls
+// of a block: a slow thread may still be reading the previous call's count
+// after a fast one has cleared the counters for the next call.
 struct SweepQueue {
     uint32_t count[4];
+    // per-thread slots
     uint32_t s[kSweepBlock];
     uint64_t w[kSweepBlock], s0[kSweepBlock], s1[kSweepBlock], s2[kSweepBlock];
-    uint64_t nt0[kSweepBlock], nt2[kSweepBlock], acc[kSweepBlock], und[kSweepBlock];
+    uint64_t nt0[kSweepBlock], nt2[kSweepBlock];
+    // queue entries
+    uint32_t owner[kSweepBlock];
+    uint64_t acc[kSweepBlock], und[kSweepBlock];
 };
 
 // Spin and coupling words are addressed as base + 32-bit byte offset, so
@@ -353,46 +360,55 @@ __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, ui
     und = lo_hi(und_lo, und_hi);
 }
 
-__device__ __forceinline__ void push_word(SweepQueue& Q, uint32_t k, const WordState& st) {
-    Q.s[k] = st.s;
-    Q.w[k] = st.w;
-    Q.s0[k] = st.s0;
-    Q.s1[k] = st.s1;
-    Q.s2[k] = st.s2;
-    Q.nt0[k] = st.nt0;
-    Q.nt2[k] = st.nt2;
-    Q.acc[k] = st.acc;
-    Q.und[k] = st.und;
+__device__ __forceinline__ void put_slot(SweepQueue& Q, uint32_t o, const WordState& st) {
+    Q.s[o] = st.s;
+    Q.w[o] = st.w;
+    Q.s0[o] = st.s0;
+    Q.s1[o] = st.s1;
+    Q.s2[o] = st.s2;
+    Q.nt0[o] = st.nt0;
+    Q.nt2[o] = st.nt2;
 }
 
-__device__ __forceinline__ WordState pop_word(const SweepQueue& Q, uint32_t k) {
+__device__ __forceinline__ void push_word(SweepQueue& Q, uint32_t k, uint32_t owner, uint64_t acc,
+                                          uint64_t und) {
+    Q.owner[k] = owner;
+    Q.acc[k] = acc;
+    Q.und[k] = und;
+}
+
+// Entry k of the queue with its owner's slot.
+__device__ __forceinline__ WordState pop_word(const SweepQueue& Q, uint32_t k, uint32_t& owner) {
     WordState r;
-    r.s = Q.s[k];
-    r.w = Q.w[k];
-    r.s0 = Q.s0[k];
-    r.s1 = Q.s1[k];
-    r.s2 = Q.s2[k];
-    r.nt0 = Q.nt0[k];
-    r.nt2 = Q.nt2[k];
+    const uint32_t o = Q.owner[k];
+    owner = o;
+    r.s = Q.s[o];
+    r.w = Q.w[o];
+    r.s0 = Q.s0[o];
+    r.s1 = Q.s1[o];
+    r.s2 = Q.s2[o];
+    r.nt0 = Q.nt0[o];
+    r.nt2 = Q.nt2[o];
     r.nt1 = ~(r.nt0 | r.nt2);
     r.acc = Q.acc[k];
     r.und = Q.und[k];
     return r;
 }
 
-// A colour pass over the block's words: the first q_split Philox blocks of
-// levels for every word; then, while the words with undecided lanes fill
-// more than one wave, they are packed into the first waves of the block and
-// given one more block; the last ones (at most one wave) are finished there.
-// Far fewer waves run the long tail of levels.  Every thread of the block
-// calls this (it synchronises); `valid` is false for threads past the last
-// word.  Packing counters: one pair per call parity (see SweepQueue); within
-// a call, round j writes counter j & 1, which round j - 1 cleared after every
-// thread had read its previous value.
+// The colour-pass update of one word per thread of the block: the first
+// q_split Philox blocks of levels for every word; then, while the words with
+// undecided lanes fill more than one wave, they are packed into the first
+// waves of the block and given one more block; the last ones (at most one
+// wave) are finished there.  Far fewer waves run the long tail of levels.
+// Every thread of the block calls this (it synchronises); `valid` is false
+// for threads without a word (st is then unused).  Packing counters: one
+// pair per call parity (see SweepQueue); within a call, round j writes
+// counter j & 1, which round j - 1 cleared after every thread had read its
+// previous value.
 template <int R, bool kGlobal>
-__device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
-                                            uint32_t colour, uint32_t t, uint32_t idx, bool valid,
-                                            uint32_t q_split, SweepQueue& Q, uint32_t parity) {
+__device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
+                                            uint32_t t, WordState st, bool valid, uint32_t q_split,
+                                            SweepQueue& Q, uint32_t parity) {
     using C = Classes<R>;
     const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
     uint32_t* cnt = Q.count + 2 * (parity & 1u);
@@ -404,7 +420,7 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
     uint64_t M[C::n];
     uint32_t th[C::n];
     if (valid) {
-        WordState st = load_word<kGlobal>(G, S, colour, idx);
+        put_slot(Q, threadIdx.x, st);
         class_masks<R>(st, thr, M, th);
         uint64_t live = 0;
 #pragma unroll
@@ -413,7 +429,7 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
         st.und = live;
         compare_levels<R>(G, g, t, st.s, M, th, thr, 0, q_split, st.acc, st.und);
         if (st.und != 0)
-            push_word(Q, atomicAdd(&cnt[0], 1u), st);
+            push_word(Q, atomicAdd(&cnt[0], 1u), threadIdx.x, st.acc, st.und);
         else if (st.acc)
             store64<kGlobal>(S, st.s, st.w ^ st.acc);
     }
@@ -424,14 +440,15 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
     for (uint32_t j = 1; n > kWaveSize && q + 1 < 16; ++j, ++q) {
         const bool have = threadIdx.x < n;
         WordState r;
-        if (have) r = pop_word(Q, threadIdx.x);
+        uint32_t owner = 0;
+        if (have) r = pop_word(Q, threadIdx.x, owner);
         __syncthreads();  // every entry and count read before any is rewritten
         if (threadIdx.x == 0) cnt[(j + 1) & 1u] = 0;
         if (have) {
             class_masks<R>(r, thr, M, th);
             compare_levels<R>(G, g, t, r.s, M, th, thr, q, q + 1, r.acc, r.und);
             if (r.und != 0)
-                push_word(Q, atomicAdd(&cnt[j & 1u], 1u), r);
+                push_word(Q, atomicAdd(&cnt[j & 1u], 1u), owner, r.acc, r.und);
             else if (r.acc)
                 store64<kGlobal>(S, r.s, r.w ^ r.acc);
         }
@@ -439,7 +456,8 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
         n = __builtin_amdgcn_readfirstlane(cnt[j & 1u]);
     }
     if (threadIdx.x < n) {
-        WordState r = pop_word(Q, threadIdx.x);
+        uint32_t owner;
+        WordState r = pop_word(Q, threadIdx.x, owner);
         class_masks<R>(r, thr, M, th);
         compare_levels<R>(G, g, t, r.s, M, th, thr, q, 16, r.acc, r.und);
         r.acc |= r.und;  // equal on all 32 bits: r == thr, accepted
@@ -447,6 +465,119 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
     }
 }
 
+// One word per thread, numbered as in load_word (the fused chunk kernel).
+template <int R, bool kGlobal>
+__device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
+                                            uint32_t colour, uint32_t t, uint32_t idx, bool valid,
+                                            uint32_t q_split, SweepQueue& Q, uint32_t parity) {
+    WordState st{};
+    if (valid) st = load_word<kGlobal>(G, S, colour, idx);
+    sweep_words<R, kGlobal>(G, S, g, t, st, valid, q_split, Q, parity);
+}
+
+// Column walk: thread `item` of a slot owns column (x, y) = item mod L^2 of
+// tau tile item / L^2 (G.tile planes, tile * G.tile ... + G.tile - 1); its
+// colour-c sites there are tau = tau0 + par, tau0 + par + 2, ..., with
+// par = (c + x + y) & 1, one per step.  Offsets of the centre and its four
+// space neighbours are fixed for the walk and the slot base advances by two
+// planes per step (a block-uniform address on the scalar unit), the four
+// couplings are loaded once, and the word below the centre is the previous
+// step's word above it, so a step costs six loads and no index arithmetic.
+// Only the first step's lower neighbour and the last step's upper one can
+// wrap round tau.
+__device__ __forceinline__ uint64_t load_at(const uint64_t* base, uint32_t byte_off) {
+    return *(const uint64_t __attribute__((address_space(1)))*)((const GlobalByte*)base + byte_off);
+}
+
+// A block-uniform pointer read back through the scalar unit: the compiler
+// then forms each address as this scalar base plus a 32-bit offset inside
+// the loop instead of keeping 64-bit per-thread addresses live across it.
+template <typename T>
+__device__ __forceinline__ T* scalar_ptr(T* p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T*)(uintptr_t)lo_hi(lo, hi);
+}
+
+template <int R>
+__device__ __forceinline__ void walk_block(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
+                                           uint32_t colour, uint32_t t, uint32_t item, bool valid,
+                                           SweepQueue& Q) {
+    const uint32_t L = G.L, P = L * L, Ltau = G.Ltau;
+    const uint32_t steps = G.tile >> 1;
+    uint32_t tile = 0, col = 0;
+    if (valid) {
+        tile = fast_div(item, G.div_plane);
+        col = item - tile * P;
+    }
+    const uint32_t y = fast_div(col, G.div_row);
+    const uint32_t x = col - y * L;
+    const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+    const uint32_t xm = (x == 0) ? L - 1 : x - 1;
+    const uint32_t yp = (y + 1 == L) ? 0 : y + 1;
+    const uint32_t ym = (y == 0) ? L - 1 : y - 1;
+    const uint32_t row = y * L;
+    const uint32_t tau0 = tile * G.tile + ((colour + x + y) & 1u);
+    const uint32_t plane0 = tau0 * P;
+    // byte offsets from the step's base S + 2 k P (k = step)
+    uint32_t o_c = (plane0 + row + x) * 8u;
+    uint32_t o_xp = (plane0 + row + xp) * 8u, o_xm = (plane0 + row + xm) * 8u;
+    uint32_t o_yp = (plane0 + yp * L + x) * 8u, o_ym = (plane0 + ym * L + x) * 8u;
+    uint32_t o_tp = o_c + P * 8u;
+    // coupling words, reloaded every step (cache hits) rather than held
+    uint32_t j_c = (row + x) * 8u, j_xm = (row + xm) * 8u, j_ym = (ym * L + x) * 8u;
+    uint64_t below = 0;
+    if (valid) {
+        if (tau0 == 0) {  // the bond round tau: slice Ltau-1, sign flipped if antiperiodic
+            below = load64<true>(S, (Ltau - 1) * P + row + x);
+            if (G.anti) below = ~below;
+        } else {
+            below = load_at(S, o_c - P * 8u);
+        }
+    }
+    const uint32_t site0 = plane0 + row + x;
+#pragma unroll 1
+    for (uint32_t k = 0; k < steps; ++k) {
+        const uint64_t* Sk = scalar_ptr(S + (size_t)k * 2 * P);
+        const uint64_t* Jx = scalar_ptr(G.Jx);
+        const uint64_t* Jy = scalar_ptr(G.Jy);
+        // the offsets stay 32-bit values in the loop (scalar base + 32-bit
+        // offset addressing), not 64-bit addresses hoisted out of it
+        asm volatile("" : "+v"(o_c), "+v"(o_xp), "+v"(o_xm), "+v"(o_yp), "+v"(o_ym), "+v"(o_tp));
+        asm volatile("" : "+v"(j_c), "+v"(j_xm), "+v"(j_ym));
+        WordState st;
+        if (valid) {
+            const uint64_t w = load_at(Sk, o_c);
+            const uint64_t nxp = load_at(Sk, o_xp), nxm = load_at(Sk, o_xm);
+            const uint64_t nyp = load_at(Sk, o_yp), nym = load_at(Sk, o_ym);
+            uint64_t above;
+            if (k + 1 == steps && tau0 + 2 * k + 1 == Ltau) {  // top slice: wraps to slice 0
+                above = load64<true>(S, row + x);
+                if (G.anti) above = ~above;
+            } else {
+                above = load_at(Sk, o_tp);
+            }
+            st.s = site0 + 2 * k * P;
+            const uint64_t jxp = load_at(Jx, j_c);
+            const uint64_t jxm = load_at(Jx, j_xm);  // the -x bond is the +x bond of x-1
+            const uint64_t jyp = load_at(Jy, j_c);
+            const uint64_t jym = load_at(Jy, j_ym);
+            const uint64_t u1 = bop3<kXor3>(w, nxp, jxp), u2 = bop3<kXor3>(w, nxm, jxm);
+            const uint64_t u3 = bop3<kXor3>(w, nyp, jyp), u4 = bop3<kXor3>(w, nym, jym);
+            const uint64_t sum = bop3<kXor3>(u1, u2, u3), carry = bop3<kMajority>(u1, u2, u3);
+            st.w = w;
+            st.s0 = sum ^ u4;
+            st.s1 = bop3<kXorAnd>(carry, sum, u4);
+            st.s2 = bop3<kAnd3>(carry, sum, u4);
+            st.nt0 = bop3<kEqEq>(w, above, below);
+            st.nt1 = above ^ below;
+            st.nt2 = bop3<kNeNe>(w, above, below);
+            below = above;
+        }
+        sweep_words<R, true>(G, S, g, t, st, valid, G.q_split, Q, k);
+    }
+}
 // S: the slot's spins (global memory, or a copy in LDS).
 // parity: alternate 0/1 between consecutive calls in one block.
 template <bool kGlobal>
@@ -459,6 +590,27 @@ __device__ __forceinline__ void sweep_block_any(const GroupDev& G, uint64_t* S, 
         case 1: sweep_block<1, kGlobal>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
         case 2: sweep_block<2, kGlobal>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
         default: sweep_block<3, kGlobal>(G, S, g, colour, t, idx, valid, q_split, Q, parity); break;
+    }
+}
+
+// Slots whose tables fit none of the three seven-class regimes (never the
+// case for the tables of either ladder kind, whose couplings are positive)
+// take the fifteen-class update one word per thread, without the walk's
+// registers: thread `item` updates colour-c words item, item + n, ... with
+// n = V / tile threads per slot.
+__device__ __forceinline__ void walk_block_any(const GroupDev& G, uint64_t* S, uint32_t g,
+                                               uint32_t colour, uint32_t t, uint32_t item,
+                                               uint32_t n_items, SweepQueue& Q) {
+    const bool valid = item < n_items;
+    switch (__builtin_amdgcn_readfirstlane(G.thr[g * kThrStride + 15])) {  // slot g's regime
+        case 0: walk_block<0>(G, S, g, colour, t, item, valid, Q); break;
+        case 1: walk_block<1>(G, S, g, colour, t, item, valid, Q); break;
+        case 2: walk_block<2>(G, S, g, colour, t, item, valid, Q); break;
+        default:
+#pragma unroll 1
+            for (uint32_t k = 0; k < (G.tile >> 1); ++k)
+                sweep_block<3, true>(G, S, g, colour, t, item + k * n_items, valid, G.q_split, Q, k);
+            break;
     }
 }
 
@@ -479,9 +631,8 @@ k_half_sweep(const GroupDev G, uint32_t colour, const uint32_t* __restrict__ ctr
     const uint32_t t = __builtin_amdgcn_readfirstlane(ctr[0] + t_add);
     const uint32_t b = xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const uint32_t g = fast_div(b, G.div_blocks);  // b / gridDim.x on the scalar unit
-    const uint32_t idx = (b - g * gridDim.x) * kSweepBlock + threadIdx.x;
-    sweep_block_any<true>(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
-                    0);
+    const uint32_t item = (b - g * gridDim.x) * kSweepBlock + threadIdx.x;
+    walk_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, item, G.V >> __builtin_ctz(G.tile), Q);
 }
 
 __device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ prefix,
@@ -569,11 +720,10 @@ k_half_sweep_batched(const BatchPlan plan, uint32_t colour, const uint32_t* __re
     const BlockPlace at = locate<kSameShape>(plan, b);
     const GroupDev G = group_record<kSameShape>(plan, at.gi);
     const uint32_t local = __builtin_amdgcn_readfirstlane(at.local);
-    const uint32_t nb = sweep_blocks_per_slot(G.V);
+    const uint32_t nb = sweep_blocks_per_slot(G.V, G.tile);
     const uint32_t g = fast_div(local, G.div_blocks);  // local / nb on the scalar unit
-    const uint32_t idx = (local - g * nb) * kSweepBlock + threadIdx.x;
-    sweep_block_any<true>(G, G.spins + (size_t)g * G.V, g, colour, t, idx, idx < (G.V >> 1), G.q_split, Q,
-                    0);
+    const uint32_t item = (local - g * nb) * kSweepBlock + threadIdx.x;
+    walk_block_any(G, G.spins + (size_t)g * G.V, g, colour, t, item, G.V >> __builtin_ctz(G.tile), Q);
 }
 
 // ---------------------------------------------------------------------------
@@ -698,45 +848,70 @@ __device__ __forceinline__ uint32_t lane_total(const LaneCounter<NH>& c) {
     return tot;
 }
 
-template <int kWords>
-__device__ __forceinline__ void energy_block(const GroupDev& G, uint32_t g, uint32_t blk,
-                                             int32_t* __restrict__ cnt) {
-    static_assert(kWords % 8 == 0, "words come in chunks of eight");
-    const uint32_t L = G.L, P = L * L, V = G.V;
-    const uint64_t* __restrict__ S = G.spins + (size_t)g * V;
-    // per thread and lane at most 2*kWords unsatisfied space bonds and
-    // kWords time bonds or differing pairs
-    LaneCounter<counter_planes(2 * kWords)> Csp;
-    LaneCounter<counter_planes(kWords)> Ct, Cq;
-    const uint32_t first = blk * (kEnergyBlock * kWords) + threadIdx.x;
+// Column walk: thread `item` of slot g owns column (x, y) = item mod L^2 of
+// tau tile item / L^2 (`planes` planes, planes dividing Ltau) and walks it
+// bottom to top.  Each bond is counted once, from its lower endpoint: per
+// word the +x and +y neighbours in the same plane and the word above, which
+// is the next step's centre, so a step costs three loads; the offsets are
+// fixed for the walk and the slot base advances one plane per step.  Eight
+// steps are loaded before their planes enter the counters.  Only the tile's
+// last bond can wrap round tau.
+template <int kMaxPlanes>
+__device__ __forceinline__ void energy_walk(const GroupDev& G, uint32_t g, uint32_t item,
+                                            uint32_t planes, int32_t* __restrict__ cnt) {
+    const uint32_t L = G.L, P = L * L;
+    const uint64_t* __restrict__ S = G.spins + (size_t)g * G.V;
+    // per thread and lane at most 2*kMaxPlanes unsatisfied space bonds and
+    // kMaxPlanes time bonds or differing pairs
+    LaneCounter<counter_planes(2 * kMaxPlanes)> Csp;
+    LaneCounter<counter_planes(kMaxPlanes)> Ct, Cq;
+    if (item < (G.V >> __builtin_ctz(planes))) {
+        const uint32_t tile = fast_div(item, G.div_plane);
+        const uint32_t col = item - tile * P;
+        const uint32_t y = fast_div(col, G.div_row);
+        const uint32_t x = col - y * L;
+        const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+        const uint32_t yp = (y + 1 == L) ? 0 : y + 1;
+        const uint32_t base = tile * planes * P;
+        uint32_t o_c = (base + col) * 8u, o_up = o_c + P * 8u;
+        uint32_t o_xp = (base + y * L + xp) * 8u, o_yp = (base + yp * L + x) * 8u;
+        const uint64_t jx = G.Jx[col], jy = G.Jy[col];
+        const bool top = tile * planes + planes == G.Ltau;  // the last bond wraps to slice 0
+        uint64_t w = load_at(S, o_c);
 #pragma unroll 1
-    for (int k0 = 0; k0 < kWords; k0 += 8) {
-        uint64_t xs[8], ys[8], ts[8], qs[8];
+        for (uint32_t k0 = 0; k0 < planes; k0 += 8) {
+            asm volatile("" : "+v"(o_up), "+v"(o_xp), "+v"(o_yp));  // 32-bit offsets in the loop
+            uint64_t xs[8], ys[8], ts[8], qs[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t s = first + (uint32_t)(k0 + k) * kEnergyBlock;
-            xs[k] = ys[k] = ts[k] = qs[k] = 0;
-            if (s < V) {
-                const uint32_t tau = fast_div(s, G.div_plane);
-                const uint32_t rem = s - tau * P;
-                const uint32_t y = fast_div(rem, G.div_row);
-                const uint32_t x = rem - y * L;
-                const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-                const uint32_t yp = (y + 1 == L) ? 0 : y + 1;
-                const uint32_t tp = (tau + 1 == G.Ltau) ? 0 : tau + 1;
-                const uint64_t w = S[s];
-                xs[k] = w ^ S[tau * P + y * L + xp] ^ G.Jx[rem];  // +x bond unsatisfied
-                ys[k] = w ^ S[tau * P + yp * L + x] ^ G.Jy[rem];  // +y bond unsatisfied
-                ts[k] = w ^ S[tp * P + rem];                        // +tau bond unsatisfied
-                if (G.anti && tp == 0) ts[k] = ~ts[k];              // antiperiodic wrap bond
-                qs[k] = (w ^ (w >> 1)) & 0x5555555555555555ull;     // pair (2p, 2p+1) differs
+            for (int k = 0; k < 8; ++k) {
+                xs[k] = ys[k] = ts[k] = qs[k] = 0;
+                if (k0 + k < planes) {  // block-uniform
+                    const uint64_t* Sk = scalar_ptr(S + (size_t)(k0 + k) * P);
+                    const uint64_t nxp = load_at(Sk, o_xp), nyp = load_at(Sk, o_yp);
+                    uint64_t up;
+                    if (top && k0 + k + 1 == planes) {
+                        up = load64<true>(S, col);
+                        if (G.anti) up = ~up;  // antiperiodic wrap bond
+                    } else {
+                        up = load_at(Sk, o_up);
+                    }
+                    xs[k] = bop3<kXor3>(w, nxp, jx);  // +x bond unsatisfied
+                    ys[k] = bop3<kXor3>(w, nyp, jy);  // +y bond unsatisfied
+                    ts[k] = w ^ up;                   // +tau bond unsatisfied
+                    // pair (2p, 2p+1) differs; pairs never straddle the halves
+                    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+                    qs[k] = lo_hi(BITOP3(lo, lo >> 1, 0x55555555u, 0x28),
+                                  BITOP3(hi, hi >> 1, 0x55555555u, 0x28));
+                    w = up;
+                }
             }
+            add8(Csp, xs);
+            add8(Csp, ys);
+            add8(Ct, ts);
+            add8(Cq, qs);
         }
-        add8(Csp, xs);
-        add8(Csp, ys);
-        add8(Ct, ts);
-        add8(Cq, qs);
     }
+    // every thread of the wave takes part in the transposes
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t my_sp = lane_total(Csp), my_t = lane_total(Ct);
     const uint32_t my_q = lane_total(Cq);  // pair p's total sits at lane 2p
@@ -747,8 +922,9 @@ __device__ __forceinline__ void energy_block(const GroupDev& G, uint32_t g, uint
 }
 
 __global__ void __launch_bounds__(kEnergyBlock)
-k_energy(const GroupDev G, int32_t* cnt) {
-    energy_block<kEnergyWordsSlot>(G, blockIdx.y, blockIdx.x, cnt);
+k_energy(const GroupDev G, int32_t* cnt, uint32_t planes) {
+    energy_walk<kEnergyPlanesSlot>(G, blockIdx.y, blockIdx.x * kEnergyBlock + threadIdx.x, planes,
+                                   cnt);
 }
 
 __global__ void __launch_bounds__(kEnergyBlock)
@@ -756,9 +932,9 @@ k_energy_batched(const BatchPlan plan) {
     const BlockPlace at = locate<false>(plan, blockIdx.x);
     const GroupDev G = group_record<false>(plan, at.gi);
     const uint32_t local = at.local;
-    const uint32_t nb = energy_blocks_per_slot(G.V, kEnergyWords);
+    const uint32_t nb = energy_blocks_per_slot(G.V, G.etile);
     const uint32_t g = local / nb;
-    energy_block<kEnergyWords>(G, g, local - g * nb, G.cnt);
+    energy_walk<kEnergyWords>(G, g, (local - g * nb) * kEnergyBlock + threadIdx.x, G.etile, G.cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1043,13 +1219,14 @@ hipError_t launch_init_state(const GroupDev& g, hipStream_t s) {
 }
 hipError_t launch_half_sweep(const GroupDev& g, uint32_t colour, const uint32_t* ctr,
                              uint32_t t_add, hipStream_t s) {
-    hipLaunchKernelGGL(k_half_sweep, dim3(sweep_blocks_per_slot(g.V), g.N), dim3(kSweepBlock), 0, s,
+    hipLaunchKernelGGL(k_half_sweep, dim3(sweep_blocks_per_slot(g.V, g.tile), g.N), dim3(kSweepBlock), 0, s,
                        g, colour, ctr, t_add);
     return hipGetLastError();
 }
 hipError_t launch_energy(const GroupDev& g, int32_t* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy, dim3(energy_blocks_per_slot(g.V, kEnergyWordsSlot), g.N),
-                       dim3(kEnergyBlock), 0, s, g, cnt);
+    const uint32_t planes = tile_for(g.Ltau, kEnergyPlanesSlot);
+    hipLaunchKernelGGL(k_energy, dim3(energy_blocks_per_slot(g.V, planes), g.N),
+                       dim3(kEnergyBlock), 0, s, g, cnt, planes);
     return hipGetLastError();
 }
 hipError_t launch_pt(const GroupDev& g, const uint32_t* ctr, uint32_t p_add, hipStream_t s) {

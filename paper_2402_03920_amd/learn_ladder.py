@@ -35,6 +35,13 @@ def _features_of(ens, groups) -> np.ndarray:
     return np.stack(X)
 
 
+def _features_of_groups(groups) -> np.ndarray:
+    """Features of groups that are not running (couplings built on the GPU
+    in a throwaway context)."""
+    with qsg.Ensemble(groups, pt_every=10, swaplog_cap=1) as ens:
+        return _features_of(ens, groups)
+
+
 def collect(groups, sweeps: int, pt_every: int = 10, flags=None, log=print):
     """Run groups with their own ladders; return features, targets and the
     acceptance of every pair over the second half of the run."""

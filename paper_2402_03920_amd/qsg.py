@@ -56,7 +56,7 @@ class qsg_group_desc(C.Structure):
 
 class qsg_run_config(C.Structure):
     _fields_ = [("pt_every", C.c_uint32), ("swaplog_cap", C.c_uint32),
-                ("sweep_split", C.c_uint32), ("reserved", C.c_uint32)]
+                ("sweep_split", C.c_uint32), ("tau_tile", C.c_uint32)]
 
 
 ROUNDTRIP_DTYPE = np.dtype([("state", "<u4"), ("t_last", "<u4"), ("count", "<u4"),
@@ -105,6 +105,7 @@ _SIGS = {
                                        C.c_void_p, C.c_void_p, C.c_void_p]),
     "qsg_set_deadline": (C.c_int32, [C.c_void_p, C.c_double]),
     "qsg_set_schedule": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32]),
+    "qsg_set_colour_schedule": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32]),
     "qsg_sync": (C.c_int32, [C.c_void_p]),
     "qsg_last_error": (C.c_char_p, [C.c_void_p]),
     "qsg_destroy": (None, [C.c_void_p]),
@@ -225,7 +226,8 @@ class Ensemble:
     """
 
     def __init__(self, groups: Sequence, pt_every: int = 10, swaplog_cap: int = 1024,
-                 swap_table_cap: int = 0, stream=None, device=None, sweep_split: int = 0):
+                 swap_table_cap: int = 0, stream=None, device=None, sweep_split: int = 0,
+                 tau_tile: int = 0):
         import torch  # device memory and streams only
         self._torch = torch
         L_ = lib()
@@ -237,7 +239,8 @@ class Ensemble:
                                       g.mc_seed, g.j_seeds, swap_table_cap,
                                       getattr(g, "ladder", "gamma"),
                                       getattr(g, "antiperiodic", False))
-        self.cfg = qsg_run_config(int(pt_every), int(swaplog_cap), int(sweep_split), 0)
+        self.cfg = qsg_run_config(int(pt_every), int(swaplog_cap), int(sweep_split),
+                                  int(tau_tile))
         nbytes = L_.qsg_workspace_bytes(self.descs, self.n, C.byref(self.cfg))
         if nbytes == 0:
             raise QSGError(QSG_E_INVALID, "invalid group description")
@@ -328,8 +331,12 @@ class Ensemble:
     def sync(self):
         _check(lib().qsg_sync(self.ctx), self.ctx)
 
-    def set_schedule(self, i: int, sweep_split: int):
-        _check(lib().qsg_set_schedule(self.ctx, int(i), int(sweep_split)), self.ctx)
+    def set_schedule(self, i: int, sweep_split: int, tau_tile: int | None = None):
+        if tau_tile is None:
+            _check(lib().qsg_set_schedule(self.ctx, int(i), int(sweep_split)), self.ctx)
+        else:
+            _check(lib().qsg_set_colour_schedule(self.ctx, int(i), int(sweep_split),
+                                                 int(tau_tile)), self.ctx)
 
     def set_deadline(self, seconds: float):
         _check(lib().qsg_set_deadline(self.ctx, float(seconds)), self.ctx)

@@ -107,9 +107,14 @@ def gpu_record(ens, i, cache=None):
                         c["accepts"][i], c["logs"][i], c["rts"][i], c["sums"][i], c["hists"][i])
 
 
+STATE_KEYS = ("t", "p", "spins", "Bsp", "Bt", "walker", "rt", "sums", "hist", "acc", "swaplog")
+
+
 def compare_records(got, want, name):
-    """Assert two records are equal, naming the first field that differs."""
-    for key in want:
+    """Assert the state fields of two records are equal (the stored record
+    also carries the case's description), naming the first that differs."""
+    assert all(k in want for k in STATE_KEYS[:9]), f"{name}: stored record incomplete"
+    for key in (k for k in STATE_KEYS if k in want):
         if key == "spins":
             bad = [g for g, (a, b) in enumerate(zip(got["spins"], want["spins"])) if a != b]
             assert not bad and len(got["spins"]) == len(want["spins"]), \

@@ -1,10 +1,15 @@
-"""GPU checks of the ladder MLP kernels against the float64 oracle.
+"""GPU checks of the ladder MLP kernels against the float64 oracle, and of
+what the trained network changes in a PT run.
 
 FP32 path (no BF16 copy): forward and gradients within 1e-5 relative; BF16
 path: within 1e-2 relative (operand rounding to bfloat16 can differ where the
 two sides' FP32/FP64 values straddle a rounding boundary).  Plus: decode,
-Adam, a training run whose loss falls, and the learned ladder's gain over the
-geometric ladder on a small ensemble.
+Adam, a training run whose loss falls, and a network trained on the GPU
+from exchange acceptance measured on the GPU, compared with the geometric
+ladder on the L = 12 samples of the learned-ladder evaluation set: the
+learned ladders equalise the exchange acceptance within a sample (asserted);
+their round-trip rate is reported with its error and not asserted, because
+no gain is measured there (parity unpinned: an empirical claim).
 """
 import math
 
@@ -65,6 +70,22 @@ def test_forward_loss_backward_match_oracle(bf16, tol):
         for size in (k * n, n):
             assert _rel(g[off:off + size], og[off:off + size]) < tol, (k, n, size)
             off += size
+    if not bf16:
+        # element by element, small entries included: an FP32 dot product of
+        # length K is within ~K * 2^-24 of the sum of its terms' magnitudes,
+        # and the inputs' own FP32 errors add the same order; 1e-5 of the
+        # magnitude sum covers both for K <= 128
+        W4 = omlp.split(p32)[3][0]
+        h3 = cache["inputs"][3]
+        mag_out = np.abs(h3) @ np.abs(W4) + np.abs(omlp.split(p32)[3][1])
+        err = np.abs(out.cpu().numpy() - cache["out"])
+        assert np.all(err <= 1e-5 * mag_out), float((err / mag_out).max())
+        dzf = odz.astype(np.float32).astype(np.float64)
+        mag_gw4 = np.abs(h3).T @ np.abs(dzf)
+        off4 = sum(k * n + n for k, n in omlp.SIZES[:3])
+        gw4 = g[off4:off4 + 128 * 32].reshape(128, 32)
+        err = np.abs(gw4 - og[off4:off4 + 128 * 32].reshape(128, 32))
+        assert np.all(err <= 1e-5 * mag_gw4 + 1e-30), float((err / (mag_gw4 + 1e-30)).max())
 
 
 def test_adam_matches_oracle():
@@ -117,3 +138,44 @@ def test_uniform_acceptance_targets_are_the_geometric_ladder():
     inc, logL = ladder.targets_from_acceptance(lad, np.full(23, 0.6))
     assert np.allclose(inc, 1.0 / 31, atol=1e-6)
     assert abs(logL - math.log(23 * 0.4)) < 1e-9
+
+
+def test_trained_network_equalises_exchange_acceptance():
+    """Train the network (GPU kernels) on the acceptance of 24 fresh L = 12
+    samples run with the geometric ladder, then run the 34 L = 12 samples of
+    the evaluation set with both ladders from the same spins and random
+    numbers (2*10^4 sweeps, PT every 10).  Where the learned ladder passes
+    the 0.2 floor it must lower the spread of the pairs' acceptance within
+    a sample and raise its smallest acceptance."""
+    from dataclasses import replace
+    from paper_2402_03920_amd import learn_ladder
+    lad = W.geometric_ladder(2.0, 4.0, 32)
+    train = [W.Group(12, 256, 16.0, lad, i, W.MC_SEED, [20001 + i] * 64) for i in range(24)]
+    X, T, logL, _ = learn_ladder.collect(train, 4000, log=lambda *a: None)
+    net = ladder.LadderMLP(seed=0, bf16=True)
+    hist = net.fit(X, T, logL, steps=1500, lr=2e-3, log_every=500)
+    assert hist[-1] < hist[0]
+    ev = [g for g in W.ladder_eval().groups if g.L == 12]
+    assert len(ev) >= 20
+    Xe = learn_ladder._features_of_groups(ev)
+    gmin = np.array([g.gammas[0] for g in ev])
+    gmax = np.array([g.gammas[-1] for g in ev])
+    pred, acc_pred = net.predict(Xe, gmin, gmax)
+    chosen, used = ladder.choose(pred, acc_pred, gmin, gmax, 0.2)
+    assert used.mean() >= 0.5, f"learned ladder used on {used.sum()} of {len(ev)} samples"
+    sweeps = 20000
+    geo = ladder.run_and_measure(ev, sweeps)
+    lrn = ladder.run_and_measure([replace(g, gammas=chosen[i]) for i, g in enumerate(ev)], sweeps)
+    ag = np.stack(geo.acc_rate)[used]
+    al = np.stack(lrn.acc_rate)[used]
+    spread_g, spread_l = ag.std(axis=1), al.std(axis=1)
+    d = lrn.rt_count.astype(float) - geo.rt_count.astype(float)
+    print(f"[ladder gain] {used.sum()} of {len(ev)} samples on the learned ladder; "
+          f"acceptance spread {spread_g.mean():.4f} -> {spread_l.mean():.4f}, "
+          f"minimum {ag.min(axis=1).mean():.4f} -> {al.min(axis=1).mean():.4f}; "
+          f"round trips {int(geo.rt_count.sum())} -> {int(lrn.rt_count.sum())}, "
+          f"paired gain {d.mean():.2f} +- {d.std(ddof=1) / math.sqrt(len(d)):.2f} per sample",
+          flush=True)
+    assert spread_l.mean() < 0.8 * spread_g.mean()
+    assert np.mean(spread_l < spread_g) >= 0.7
+    assert al.min(axis=1).mean() > ag.min(axis=1).mean()

@@ -348,18 +348,27 @@ def test_modes_agree_on_uneven_ensemble():
         assert np.array_equal(states["plain"], states[mode]), mode
 
 
-@pytest.mark.parametrize("split", [1, 2, 3, 5, 8, 16])
-def test_every_schedule_gives_the_same_trajectory(split):
-    """The colour-pass schedule (when undecided words are packed) only moves
-    work between waves: the trajectory is identical for every value, per
-    group and per ensemble."""
+@pytest.mark.parametrize("split,tile", [(1, 2), (2, 4), (3, 8), (5, 16), (8, 32), (16, 8),
+                                        (4, 2), (4, 32)])
+def test_every_schedule_gives_the_same_trajectory(split, tile):
+    """The colour-pass schedule -- when undecided words are packed, and how
+    many tau planes one thread walks along its column -- only moves work
+    between waves and threads: the trajectory is identical for every value,
+    per group and per ensemble, in per-group and batched launches."""
     groups = small_groups() + W.uneven_ensemble(n_samples=3).groups
     with qsg.Ensemble(groups, pt_every=5, swaplog_cap=8) as ref:
         ref.init_spins()
         ref.sweep(20, qsg.QSG_BATCHED)
         want = ref.get_state()
+    for flags in (qsg.QSG_BATCHED | qsg.QSG_GRAPH, qsg.QSG_PLAIN):
+        with qsg.Ensemble(groups, pt_every=5, swaplog_cap=8, sweep_split=split,
+                          tau_tile=tile) as ens:
+            ens.set_schedule(0, 16, 2)
+            ens.set_schedule(len(groups) - 1, 3, 16)
+            ens.init_spins()
+            ens.sweep(20, flags)
+            assert np.array_equal(ens.get_state(), want), (split, tile, flags)
     with qsg.Ensemble(groups, pt_every=5, swaplog_cap=8, sweep_split=split) as ens:
-        ens.set_schedule(0, 16)
         ens.init_spins()
         ens.sweep(20, qsg.QSG_BATCHED | qsg.QSG_FUSED)
         assert np.array_equal(ens.get_state(), want)
