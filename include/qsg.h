@@ -483,6 +483,21 @@ qsg_status qsg_mlp_forward(const float* d_params, const uint16_t* d_params_bf16,
                            const float* d_x, uint32_t B, float* d_out, float* d_ws,
                            void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * forward pass as qsg_mlp_forward, bit for bit, with its workspace in a
+ * fixed device array of the library (QSG_MLP_NOALLOC_MAX_BATCH * 800 floats,
+ * 3.2 MB, one copy per GPU, held until the process ends) instead of d_ws.
+ * The caller passes parameters, inputs and outputs.  No allocation happens
+ * in this call.  The array's address is looked up on the first call on each
+ * device.  Calls on one GPU share that GPU's array, so calls that overlap
+ * on one GPU (other streams, other threads) race; serialise them.
+ * QSG_E_INVALID for null pointers, B = 0 or B > QSG_MLP_NOALLOC_MAX_BATCH
+ * (nothing is launched); QSG_E_DEVICE if the lookup or a launch fails. */
+#define QSG_MLP_NOALLOC_MAX_BATCH 1024
+qsg_status qsg_mlp_forward_noalloc(const float* d_params, const uint16_t* d_params_bf16,
+                                   const float* d_x, uint32_t B, float* d_out, void* hip_stream);
+
 /* Gradients of a scalar loss w.r.t. the FP32 parameters, given dL/d(out)
  * d_dout[B][32] and the forward workspace of the same batch.
  * d_scratch: 2*B*128 floats.  d_grads: qsg_mlp_param_count() floats. */

@@ -28,6 +28,7 @@ extern "C" int qsg_tables_build_host_k(uint32_t N, const double* k, uint32_t cap
                                        size_t errlen);
 
 static_assert(qsg::kMaxSlots == QSG_MAX_GAMMA, "kernels size per-group arrays by the slot limit");
+static_assert(qsg::kMlpNoAllocMaxBatch == QSG_MLP_NOALLOC_MAX_BATCH, "one batch limit for the allocation-free forward");
 
 namespace {
 
@@ -1074,6 +1075,18 @@ qsg_status qsg_mlp_forward(const float* d_params, const uint16_t* d_params_bf16,
     return mlp_status(qsg::mlp_forward(d_params, d_params_bf16, d_x, (int)B, d_out, d_ws,
                                        static_cast<hipStream_t>(hip_stream)),
                       "mlp_forward");
+}
+
+qsg_status qsg_mlp_forward_noalloc(const float* d_params, const uint16_t* d_params_bf16,
+                                   const float* d_x, uint32_t B, float* d_out, void* hip_stream) {
+    if (!d_params || !d_x || !d_out || B < 1)
+        return fail(nullptr, QSG_E_INVALID, "mlp_forward_noalloc: null buffer or empty batch");
+    if (B > (uint32_t)qsg::kMlpNoAllocMaxBatch)
+        return fail(nullptr, QSG_E_INVALID, "mlp_forward_noalloc: batch %u exceeds the limit %d",
+                    B, qsg::kMlpNoAllocMaxBatch);
+    return mlp_status(qsg::mlp_forward_noalloc(d_params, d_params_bf16, d_x, (int)B, d_out,
+                                               static_cast<hipStream_t>(hip_stream)),
+                      "mlp_forward_noalloc");
 }
 
 qsg_status qsg_mlp_backward(const float* d_params, const uint16_t* d_params_bf16, const float* d_x,

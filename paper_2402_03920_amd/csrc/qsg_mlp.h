@@ -30,6 +30,11 @@ __host__ __device__ inline size_t mlp_ws_floats(int B) {
 
 hipError_t mlp_forward(const float* pf, const uint16_t* ph, const float* x, int B, float* out,
                        float* ws, hipStream_t s);
+// The same forward with its workspace in the library's fixed per-device
+// array (batches of at most kMlpNoAllocMaxBatch; no allocation).
+constexpr int kMlpNoAllocMaxBatch = 1024;
+hipError_t mlp_forward_noalloc(const float* pf, const uint16_t* ph, const float* x, int B,
+                               float* out, hipStream_t s);
 hipError_t mlp_backward(const float* pf, const uint16_t* ph, const float* x, const float* ws,
                         const float* dout, int B, float* grads, float* scratch, hipStream_t s);
 hipError_t mlp_loss(const float* z, const float* t, const float* logL, int B, float* dz,

@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "qsg_mlp.h"
 
@@ -265,6 +266,49 @@ hipError_t mlp_decode(const float* z, const double* gmin, const double* gmax, in
     hipLaunchKernelGGL(k_decode, dim3(blocks(B, 64)), dim3(64), 0, s, z, gmin, gmax, B, ladder,
                        acc_pred);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Forward pass that allocates nothing: the activations live in a fixed
+// device array of this library (one copy per GPU, held until the process
+// ends) instead of a caller workspace.  In host code `scratch` names a
+// host-side stand-in, not the device copy: its device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current,
+// and only that address is ever passed to kernels.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) float scratch[(size_t)kMlpNoAllocMaxBatch * (6 * kMlpHidden + kMlpOut)];
+static_assert(sizeof(scratch) / sizeof(float) >= (size_t)6 * kMlpNoAllocMaxBatch * kMlpHidden +
+                                                       (size_t)kMlpNoAllocMaxBatch * kMlpOut,
+              "scratch must hold the forward workspace of the largest batch");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t mlp_noalloc_scratch(float** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t mlp_forward_noalloc(const float* pf, const uint16_t* ph, const float* x, int B,
+                               float* out, hipStream_t s) {
+    float* ws = nullptr;
+    hipError_t e = mlp_noalloc_scratch(&ws);
+    if (e != hipSuccess) return e;
+    return mlp_forward(pf, ph, x, B, out, ws, s);
 }
 
 }  // namespace qsg

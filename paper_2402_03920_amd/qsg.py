@@ -128,6 +128,8 @@ _SIGS = {
                                            C.c_size_t, C.c_void_p, C.c_void_p]),
     "qsg_mlp_param_count": (C.c_uint32, []),
     "qsg_mlp_workspace_floats": (C.c_size_t, [C.c_uint32]),
+    "qsg_mlp_forward_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                                            C.c_void_p, C.c_void_p]),
     "qsg_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "qsg_mlp_backward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -602,6 +604,11 @@ def _stream_ptr():
 def qsg_mlp_forward(params, params_bf16, x, out, ws):
     _check(lib().qsg_mlp_forward(_dp(params), _dp(params_bf16), _dp(x), x.shape[0], _dp(out),
                                  _dp(ws), _stream_ptr()))
+
+
+def qsg_mlp_forward_noalloc(params, params_bf16, x, out):
+    _check(lib().qsg_mlp_forward_noalloc(_dp(params), _dp(params_bf16), _dp(x), x.shape[0],
+                                         _dp(out), _stream_ptr()))
 
 
 def qsg_mlp_backward(params, params_bf16, x, ws, dout, grads, scratch):
