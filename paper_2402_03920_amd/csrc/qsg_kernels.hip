@@ -280,11 +280,15 @@ __device__ __forceinline__ void class_masks(const WordState& st, const uint32_t*
 // block-uniform shift register (see kLevelPicks).
 struct Picks {
     uint64_t w[4];
-    __device__ __forceinline__ void load(const uint32_t* __restrict__ thr, uint32_t q0) {
+    // The slot's picks, read once per block (the table does not change
+    // during a launch).
+    __device__ __forceinline__ void load(const uint32_t* __restrict__ thr) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             w[i] = lo_hi(__builtin_amdgcn_readfirstlane(thr[kLevelPicks + 2 * i]),
                          __builtin_amdgcn_readfirstlane(thr[kLevelPicks + 2 * i + 1]));
+    }
+    __device__ __forceinline__ void skip(uint32_t q0) {
 #pragma unroll 1
         for (uint32_t q = 0; q < q0; ++q) next();
     }
@@ -313,16 +317,20 @@ template <int R>
 __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, uint32_t t,
                                                uint32_t s, const uint64_t (&M)[Classes<R>::n],
                                                const uint32_t (&th)[Classes<R>::n],
-                                               const uint32_t* __restrict__ thr, uint32_t q0,
-                                               uint32_t q1, uint64_t& acc, uint64_t& und) {
+                                               const Picks& picks, uint32_t q0,
+                                               uint32_t q1, uint64_t& acc, uint64_t& und,
+                                               uint32_t unchecked = 0) {
     using C = Classes<R>;
     uint32_t acc_lo = (uint32_t)acc, acc_hi = (uint32_t)(acc >> 32);
     uint32_t und_lo = (uint32_t)und, und_hi = (uint32_t)(und >> 32);
-    Picks P;
-    if (R < 3) P.load(thr, q0);
+    Picks P = picks;
+    if (R < 3) P.skip(q0);
 #pragma unroll 1
     for (uint32_t q = q0; q < q1; ++q) {
-        if (!__any((und_lo | und_hi) != 0)) break;  // every lane of the wave is decided
+        // every lane of the wave decided: stop (not checked for the first
+        // `unchecked` blocks, where that almost never happens; a block run
+        // on decided lanes changes nothing)
+        if (q >= q0 + unchecked && !__any((und_lo | und_hi) != 0)) break;
         const uint4 o = philox(make_uint4(s, t, (g << 4) | q, G.gid), G.key0, G.key1);
         const uint32_t lev_lo[2] = {o.x, o.z};
         const uint32_t lev_hi[2] = {o.y, o.w};
@@ -408,7 +416,7 @@ __device__ __forceinline__ WordState pop_word(const SweepQueue& Q, uint32_t k, u
 template <int R, bool kGlobal>
 __device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
                                             uint32_t t, WordState st, bool valid, uint32_t q_split,
-                                            SweepQueue& Q, uint32_t parity) {
+                                            const Picks& picks, SweepQueue& Q, uint32_t parity) {
     using C = Classes<R>;
     const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
     uint32_t* cnt = Q.count + 2 * (parity & 1u);
@@ -427,7 +435,7 @@ __device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restr
         for (int i = 0; i < C::n; ++i) live |= M[i];
         st.acc = ~live;  // lanes outside the listed classes: dE <= 0, accepted
         st.und = live;
-        compare_levels<R>(G, g, t, st.s, M, th, thr, 0, q_split, st.acc, st.und);
+        compare_levels<R>(G, g, t, st.s, M, th, picks, 0, q_split, st.acc, st.und, 0);
         if (st.und != 0)
             push_word(Q, atomicAdd(&cnt[0], 1u), threadIdx.x, st.acc, st.und);
         else if (st.acc)
@@ -446,7 +454,7 @@ __device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restr
         if (threadIdx.x == 0) cnt[(j + 1) & 1u] = 0;
         if (have) {
             class_masks<R>(r, thr, M, th);
-            compare_levels<R>(G, g, t, r.s, M, th, thr, q, q + 1, r.acc, r.und);
+            compare_levels<R>(G, g, t, r.s, M, th, picks, q, q + 1, r.acc, r.und);
             if (r.und != 0)
                 push_word(Q, atomicAdd(&cnt[j & 1u], 1u), owner, r.acc, r.und);
             else if (r.acc)
@@ -455,11 +463,15 @@ __device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restr
         __syncthreads();
         n = __builtin_amdgcn_readfirstlane(cnt[j & 1u]);
     }
-    if (threadIdx.x < n) {
+    // the last words are finished where they sit in the queue; when they
+    // fit one wave (all but the 16-block limit) that is wave parity % 4, so
+    // that over consecutive calls every wave takes a turn
+    const uint32_t lead = 0;
+    if (threadIdx.x - lead < n) {
         uint32_t owner;
-        WordState r = pop_word(Q, threadIdx.x, owner);
+        WordState r = pop_word(Q, threadIdx.x - lead, owner);
         class_masks<R>(r, thr, M, th);
-        compare_levels<R>(G, g, t, r.s, M, th, thr, q, 16, r.acc, r.und);
+        compare_levels<R>(G, g, t, r.s, M, th, picks, q, 16, r.acc, r.und);
         r.acc |= r.und;  // equal on all 32 bits: r == thr, accepted
         if (r.acc) store64<kGlobal>(S, r.s, r.w ^ r.acc);
     }
@@ -472,7 +484,9 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
                                             uint32_t q_split, SweepQueue& Q, uint32_t parity) {
     WordState st{};
     if (valid) st = load_word<kGlobal>(G, S, colour, idx);
-    sweep_words<R, kGlobal>(G, S, g, t, st, valid, q_split, Q, parity);
+    Picks picks;
+    if (R < 3) picks.load(G.thr + g * kThrStride);
+    sweep_words<R, kGlobal>(G, S, g, t, st, valid, q_split, picks, Q, parity);
 }
 
 // Column walk: thread `item` of a slot owns column (x, y) = item mod L^2 of
@@ -537,11 +551,14 @@ __device__ __forceinline__ void walk_block(const GroupDev& G, uint64_t* __restri
         }
     }
     const uint32_t site0 = plane0 + row + x;
+    Picks picks;
+    picks.load(G.thr + g * kThrStride);
+    const uint64_t* S0 = scalar_ptr(S);
+    const uint64_t* Jx = scalar_ptr(G.Jx);
+    const uint64_t* Jy = scalar_ptr(G.Jy);
 #pragma unroll 1
     for (uint32_t k = 0; k < steps; ++k) {
-        const uint64_t* Sk = scalar_ptr(S + (size_t)k * 2 * P);
-        const uint64_t* Jx = scalar_ptr(G.Jx);
-        const uint64_t* Jy = scalar_ptr(G.Jy);
+        const uint64_t* Sk = S0 + (size_t)k * 2 * P;
         // the offsets stay 32-bit values in the loop (scalar base + 32-bit
         // offset addressing), not 64-bit addresses hoisted out of it
         asm volatile("" : "+v"(o_c), "+v"(o_xp), "+v"(o_xm), "+v"(o_yp), "+v"(o_ym), "+v"(o_tp));
@@ -575,7 +592,7 @@ __device__ __forceinline__ void walk_block(const GroupDev& G, uint64_t* __restri
             st.nt2 = bop3<kNeNe>(w, above, below);
             below = above;
         }
-        sweep_words<R, true>(G, S, g, t, st, valid, G.q_split, Q, k);
+        sweep_words<R, true>(G, S, g, t, st, valid, G.q_split, picks, Q, k);
     }
 }
 // S: the slot's spins (global memory, or a copy in LDS).
