@@ -189,7 +189,7 @@ def main():
     import torch
 
     import qsg_workloads as W
-    from paper_2402_03920_amd import qsg
+    from paper_2402_03920_amd import autotune, qsg
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -201,7 +201,6 @@ def main():
 
     schedules = {}
     if not args.no_autotune:
-        from paper_2402_03920_amd import autotune
         print("[bench] tuning the colour-pass schedule per shape", file=sys.stderr, flush=True)
         schedules = autotune.tune(wl.groups, log=lambda m: print(m, file=sys.stderr, flush=True))
     ens = qsg.Ensemble(wl.groups, pt_every=pe, swaplog_cap=64)
@@ -223,14 +222,8 @@ def main():
     # the two batched forms of a PT chunk, both replayed as a HIP graph: one
     # launch per colour pass over every group, or one fused launch for all the
     # sweeps of the chunk (a block per slot); the faster one is the value
-    forms = {"per-pass": qsg.QSG_BATCHED | qsg.QSG_GRAPH,
-             "fused": qsg.QSG_BATCHED | qsg.QSG_GRAPH | qsg.QSG_FUSED}
-    probe = {}
-    for name, fl in forms.items():
-        ens.sweep(pe, fl)  # capture + warm
-        probe[name] = timed(lambda: ens.sweep(pe * 2, fl))
-    form = min(probe, key=probe.get)
-    flags = forms[form]
+    form, flags, probe = autotune.pick_form(ens)
+    forms = autotune.FORMS
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     ens.sweep(pe * args.warmup, flags)
     torch.cuda.synchronize()
@@ -281,6 +274,7 @@ def main():
             "step": f"{pe} sweeps + energy pass + PT step + exchange pass, all samples",
             "spin_updates_per_step": upd_per_sweep * pe,
             "batched_form": form,
+            "form_ms_per_chunk": {k: round(v * 1e3, 4) for k, v in probe.items()},
             "schedules": schedules,
         },
         f"{other}_ps_per_spin_update": round(ps_other, 5),

@@ -1,26 +1,34 @@
-"""Per-shape schedule tuning of the colour pass.
+"""Per-shape schedule tuning of the colour pass, and the choice of launch form.
 
 A group's colour-pass schedule has two knobs, neither of which changes any
 result (the random numbers and decisions do not depend on them; tests check
 that every candidate gives the same trajectory):
 
+* `tau_tile`: how many tau planes one thread walks along its column (it
+  updates tau_tile/2 words).  Deep walks save loads and index work per word
+  but give fewer threads; small ensembles want shallow walks to fill the
+  chip.
 * `sweep_split`: how many Philox blocks every word goes through before the
   words whose 64 lanes are not all decided are packed into the first waves
   of the block.  Small values pack early (more words travel through LDS),
   large values leave more waves running the long tail of levels; the best
   value depends on the class mix, hence on beta and the ladder.
-* `tau_tile`: how many tau planes one thread walks along its column (it
-  updates tau_tile/2 words).  Deep walks save loads and index work per word
-  but give fewer threads; small slots want shallow walks to fill the chip.
 
 Groups are tuned by class: (L, L_tau, beta, ladder kind and end points);
-the number of ladder points only scales the work.  For each class the tuner
-builds a sub-ensemble of up to `max_groups` of its groups and times every
-candidate's batched colour passes (HIP events on the library's stream, the
-median of `repeats` runs of `sweeps` sweeps).  The fastest candidate wins
-unless the default is within `tie` of it, which keeps picks stable from run
-to run.  Whether a PT chunk runs as one launch per pass or as one fused
-launch is the other, ensemble-wide choice (bench.py times both forms).
+the number of ladder points only scales the work.  The best walk depth
+depends on how full the chip is, so a class is timed at the size of the
+whole ensemble, up to SCALE_WORDS: its groups are repeated until the timed
+sub-ensemble holds that many words (a class timed on its own would favour
+shallow walks that lose once the other classes share the chip; beyond
+2^26 words every candidate fills the chip several times over).  Per class
+the tuner first times every walk depth at the default split, then every
+split at the best depth (HIP events on the library's stream, the median of
+`repeats` runs of `sweeps` sweeps).  A candidate replaces the default only
+when it is faster by more than `tie`, which keeps picks stable from run to
+run.
+
+`pick_form` makes the other, ensemble-wide choice: whether a PT chunk runs
+as one launch per colour pass or as one fused launch for all its sweeps.
 """
 from __future__ import annotations
 
@@ -33,6 +41,7 @@ from . import qsg
 SPLITS = (3, 4, 5, 6)
 TILES = (2, 4, 8, 16, 32)
 DEFAULT = (4, 8)
+SCALE_WORDS = 1 << 26
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedules.json")
 
 
@@ -47,6 +56,26 @@ def valid_tiles(L_tau: int, tiles: Iterable[int] = TILES) -> List[int]:
     """Walk depths that are a distinct power of two dividing L_tau (the
     library takes the largest power of two <= the request dividing L_tau)."""
     return [t for t in tiles if L_tau % t == 0]
+
+
+def default_for(L_tau: int) -> Tuple[int, int]:
+    return DEFAULT[0], max(t for t in valid_tiles(L_tau) if t <= DEFAULT[1])
+
+
+def group_words(g) -> int:
+    return len(g.gammas) * g.L * g.L * g.L_tau
+
+
+def at_scale(gs: List, words: int) -> List:
+    """The class's groups, repeated in order until they hold at least
+    `words` words (at least every group once)."""
+    out, have, i = [], 0, 0
+    while i < len(gs) or have < words:
+        g = gs[i % len(gs)]
+        out.append(g)
+        have += group_words(g)
+        i += 1
+    return out
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, Tuple[int, int]]:
@@ -67,56 +96,77 @@ def _median(xs):
     return xs[len(xs) // 2]
 
 
-def time_candidates(groups, candidates, sweeps: int = 4, repeats: int = 5, warm: int = 2):
-    """Median seconds per sweep of the batched colour passes (no PT) of
-    these groups for every (sweep_split, tau_tile) candidate, all in one
-    context (the candidates are set with qsg_set_colour_schedule)."""
+def _timer(stream):
     import torch
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3
+    return timed
+
+
+def time_candidates(ens, candidates, sweeps: int = 4, repeats: int = 5):
+    """Median seconds per sweep of the ensemble's batched colour passes (no
+    PT) for every (sweep_split, tau_tile) candidate, set on every group with
+    qsg_set_colour_schedule."""
+    timed = _timer(ens.stream)
     out = {}
-    with qsg.Ensemble(groups, pt_every=0, swaplog_cap=1) as ens:
-        ens.init_spins()
-        ens.sweep(warm, qsg.QSG_BATCHED)
-        for cand in candidates:
-            for i in range(len(groups)):
-                ens.set_schedule(i, cand[0], cand[1])
-            ens.sweep(1, qsg.QSG_BATCHED)
-            times = []
-            for _ in range(repeats):
-                torch.cuda.synchronize()
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record(ens.stream)
-                ens.sweep(sweeps, qsg.QSG_BATCHED | qsg.QSG_NO_PT)
-                b.record(ens.stream)
-                torch.cuda.synchronize()
-                times.append(a.elapsed_time(b) / 1e3 / sweeps)
-            out[cand] = _median(times)
+    for cand in candidates:
+        for i in range(ens.n):
+            ens.set_schedule(i, cand[0], cand[1])
+        ens.sweep(1, qsg.QSG_BATCHED | qsg.QSG_NO_PT)
+        out[cand] = _median([timed(lambda: ens.sweep(sweeps, qsg.QSG_BATCHED | qsg.QSG_NO_PT))
+                             / sweeps for _ in range(repeats)])
     return out
 
 
+def _pick(times, default, tie):
+    best = min(times, key=times.get)
+    return default if times[default] <= times[best] * (1.0 + tie) else best
+
+
 def tune(groups, splits: Iterable[int] = SPLITS, tiles: Iterable[int] = TILES,
-         cache: Dict[str, Tuple[int, int]] | None = None, max_groups: int = 16,
-         tie: float = 0.01, log=None) -> Dict[str, Tuple[int, int]]:
-    """Best (sweep_split, tau_tile) for every class present in `groups`."""
+         cache: Dict[str, Tuple[int, int]] | None = None, tie: float = 0.01,
+         scale_words: int | None = None, log=None, report: Dict | None = None
+         ) -> Dict[str, Tuple[int, int]]:
+    """Best (sweep_split, tau_tile) for every class present in `groups`,
+    each class timed at `scale_words` words (default: the whole ensemble's,
+    at most SCALE_WORDS).
+    `report`, if given, receives per class the timings of every candidate."""
     cache = {} if cache is None else cache
     by_class: Dict[str, List] = {}
     for g in groups:
         by_class.setdefault(shape_key(g), []).append(g)
+    words = min(sum(group_words(g) for g in groups), SCALE_WORDS) if scale_words is None \
+        else scale_words
     for key, gs in by_class.items():
         if key in cache:
             continue
-        cands = [(s, t) for s in splits for t in valid_tiles(gs[0].L_tau, tiles)]
-        default = (DEFAULT[0], max(t for t in valid_tiles(gs[0].L_tau) if t <= DEFAULT[1]))
-        if default not in cands:
-            cands.append(default)
-        times = time_candidates(gs[:max_groups], cands)
-        best = min(times, key=times.get)
-        if times[default] <= times[best] * (1.0 + tie):
-            best = default
+        L_tau = gs[0].L_tau
+        default = default_for(L_tau)
+        with qsg.Ensemble(at_scale(gs, words), pt_every=0, swaplog_cap=1) as ens:
+            ens.init_spins()
+            ens.sweep(2, qsg.QSG_BATCHED | qsg.QSG_NO_PT)
+            tile_cands = sorted(set(valid_tiles(L_tau, tiles)) | {default[1]})
+            t_tiles = time_candidates(ens, [(default[0], t) for t in tile_cands])
+            tile = _pick(t_tiles, default, tie)[1]
+            base = (default[0], tile)
+            t_splits = time_candidates(ens, [(s, tile) for s in splits if s != base[0]])
+            t_splits[base] = t_tiles[base]
+            best = _pick(t_splits, base, tie)
         cache[key] = best
+        if report is not None:
+            report[key] = {"tiles": t_tiles, "splits": t_splits, "pick": best}
         if log:
-            log(f"[autotune] {key}: " + ", ".join(f"{c[0]}/{c[1]}:{t * 1e6:.1f}us"
-                                                  for c, t in sorted(times.items()))
+            log(f"[autotune] {key} at {words} words: "
+                + ", ".join(f"{c[0]}/{c[1]}:{t * 1e6:.1f}us"
+                            for c, t in sorted({**t_tiles, **t_splits}.items()))
                 + f" -> split {best[0]}, tile {best[1]}")
     return cache
 
@@ -131,3 +181,24 @@ def apply(ens, cache: Dict[str, Tuple[int, int]]) -> int:
             ens.set_schedule(i, split, tile)
             n += 1
     return n
+
+
+FORMS = {"per-pass": qsg.QSG_BATCHED | qsg.QSG_GRAPH,
+         "fused": qsg.QSG_BATCHED | qsg.QSG_GRAPH | qsg.QSG_FUSED}
+
+
+def pick_form(ens, chunks: int = 2, repeats: int = 3):
+    """The faster batched form of a PT chunk for this ensemble, both replayed
+    as HIP graphs: one launch per colour pass over every group, or one fused
+    launch per chunk (a block per slot).  Returns (name, flags, seconds per
+    chunk of each form).  Both forms give the same trajectory; timing them
+    advances the ensemble."""
+    timed = _timer(ens.stream)
+    pe = ens.cfg.pt_every
+    times = {}
+    for name, fl in FORMS.items():
+        ens.sweep(pe, fl)  # capture + warm
+        times[name] = _median([timed(lambda: ens.sweep(pe * chunks, fl)) / chunks
+                               for _ in range(repeats)])
+    name = min(times, key=times.get)
+    return name, FORMS[name], times

@@ -118,6 +118,7 @@ constexpr int kAndXnor = 0x90;    // a & ~(b ^ c)
 constexpr int kXor3 = 0x96;       // a ^ b ^ c
 constexpr int kMajority = 0xE8;   // at least two of a, b, c
 constexpr int kXorAnd = 0x78;     // a ^ (b & c)
+constexpr int kSelect = 0xCA;     // a ? b : c (bitwise)
 constexpr int kAnd3 = 0x80;       // a & b & c
 constexpr int kAndNotAnd = 0x20;  // a & ~b & c
 constexpr int kNor3 = 0x01;       // ~(a | b | c)
@@ -159,6 +160,7 @@ struct SweepQueue {
     uint32_t owner[kSweepBlock];
     uint64_t acc[kSweepBlock], und[kSweepBlock];
 };
+
 
 // Spin and coupling words are addressed as base + 32-bit byte offset, so
 // global accesses keep the base in SGPRs and only the offset in a VGPR.  The
@@ -276,31 +278,6 @@ __device__ __forceinline__ void class_masks(const WordState& st, const uint32_t*
 }
 
 
-// Level picks of the blocks q >= q0, two bytes per block, as a 256-bit
-// block-uniform shift register (see kLevelPicks).
-struct Picks {
-    uint64_t w[4];
-    // The slot's picks, read once per block (the table does not change
-    // during a launch).
-    __device__ __forceinline__ void load(const uint32_t* __restrict__ thr) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            w[i] = lo_hi(__builtin_amdgcn_readfirstlane(thr[kLevelPicks + 2 * i]),
-                         __builtin_amdgcn_readfirstlane(thr[kLevelPicks + 2 * i + 1]));
-    }
-    __device__ __forceinline__ void skip(uint32_t q0) {
-#pragma unroll 1
-        for (uint32_t q = 0; q < q0; ++q) next();
-    }
-    __device__ __forceinline__ uint32_t current() const { return (uint32_t)w[0] & 0xFFFFu; }
-    __device__ __forceinline__ void next() {
-        w[0] = (w[0] >> 16) | (w[1] << 48);
-        w[1] = (w[1] >> 16) | (w[2] << 48);
-        w[2] = (w[2] >> 16) | (w[3] << 48);
-        w[3] >>= 16;
-    }
-};
-
 // Compare the lanes' bit-sliced Philox numbers with their class thresholds,
 // most significant level first, for blocks q0 <= q < q1 while any lane of
 // the wave is undecided.  Block q (counter (s, t, g<<4 | q, gid)) carries
@@ -317,14 +294,17 @@ template <int R>
 __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, uint32_t t,
                                                uint32_t s, const uint64_t (&M)[Classes<R>::n],
                                                const uint32_t (&th)[Classes<R>::n],
-                                               const Picks& picks, uint32_t q0,
+                                               const uint32_t* thr, uint32_t q0,
                                                uint32_t q1, uint64_t& acc, uint64_t& und,
                                                uint32_t unchecked = 0) {
     using C = Classes<R>;
     uint32_t acc_lo = (uint32_t)acc, acc_hi = (uint32_t)(acc >> 32);
     uint32_t und_lo = (uint32_t)und, und_hi = (uint32_t)(und >> 32);
-    Picks P = picks;
-    if (R < 3) P.skip(q0);
+    // the slot's level picks (two bytes per block, see kLevelPicks), read
+    // through the constant address space: block-uniform scalar loads (the
+    // table is not written during a launch)
+    typedef const uint32_t __attribute__((address_space(4)))* ConstU32;
+    const ConstU32 pk = (ConstU32)(thr);
 #pragma unroll 1
     for (uint32_t q = q0; q < q1; ++q) {
         // every lane of the wave decided: stop (not checked for the first
@@ -338,7 +318,7 @@ __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, ui
         for (int h = 0; h < 2; ++h) {
             uint32_t T_lo = 0, T_hi = 0;
             if (R < 3) {
-                const uint32_t pick = (P.current() >> (8 * h)) & 0xFFu;
+                const uint32_t pick = (pk[kLevelPicks + (q >> 1)] >> (16 * (q & 1u) + 8 * h)) & 0xFFu;
                 T_lo = T_hi = 0u - (pick >> 7);
 #pragma unroll
                 for (int i = 0; i < C::n; ++i) {
@@ -362,7 +342,6 @@ __device__ __forceinline__ void compare_levels(const GroupDev& G, uint32_t g, ui
             und_lo = BITOP3(und_lo, T_lo, lev_lo[h], kAndXnor);
             und_hi = BITOP3(und_hi, T_hi, lev_hi[h], kAndXnor);
         }
-        if (R < 3) P.next();
     }
     acc = lo_hi(acc_lo, acc_hi);
     und = lo_hi(und_lo, und_hi);
@@ -414,9 +393,22 @@ __device__ __forceinline__ WordState pop_word(const SweepQueue& Q, uint32_t k, u
 // counter j & 1, which round j - 1 cleared after every thread had read its
 // previous value.
 template <int R, bool kGlobal>
+__device__ __forceinline__ void finish_word(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
+                                            uint32_t t, WordState r, uint32_t q) {
+    using C = Classes<R>;
+    const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
+    uint64_t M[C::n];
+    uint32_t th[C::n];
+    class_masks<R>(r, thr, M, th);
+    compare_levels<R>(G, g, t, r.s, M, th, thr, q, 16, r.acc, r.und);
+    r.acc |= r.und;  // equal on all 32 bits: r == thr, accepted
+    if (r.acc) store64<kGlobal>(S, r.s, r.w ^ r.acc);
+}
+
+template <int R, bool kGlobal>
 __device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
                                             uint32_t t, WordState st, bool valid, uint32_t q_split,
-                                            const Picks& picks, SweepQueue& Q, uint32_t parity) {
+                                            SweepQueue& Q, uint32_t parity) {
     using C = Classes<R>;
     const uint32_t* __restrict__ thr = G.thr + g * kThrStride;
     uint32_t* cnt = Q.count + 2 * (parity & 1u);
@@ -435,7 +427,7 @@ __device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restr
         for (int i = 0; i < C::n; ++i) live |= M[i];
         st.acc = ~live;  // lanes outside the listed classes: dE <= 0, accepted
         st.und = live;
-        compare_levels<R>(G, g, t, st.s, M, th, picks, 0, q_split, st.acc, st.und, 0);
+        compare_levels<R>(G, g, t, st.s, M, th, thr, 0, q_split, st.acc, st.und, 0);
         if (st.und != 0)
             push_word(Q, atomicAdd(&cnt[0], 1u), threadIdx.x, st.acc, st.und);
         else if (st.acc)
@@ -454,7 +446,7 @@ __device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restr
         if (threadIdx.x == 0) cnt[(j + 1) & 1u] = 0;
         if (have) {
             class_masks<R>(r, thr, M, th);
-            compare_levels<R>(G, g, t, r.s, M, th, picks, q, q + 1, r.acc, r.und);
+            compare_levels<R>(G, g, t, r.s, M, th, thr, q, q + 1, r.acc, r.und);
             if (r.und != 0)
                 push_word(Q, atomicAdd(&cnt[j & 1u], 1u), owner, r.acc, r.und);
             else if (r.acc)
@@ -463,17 +455,10 @@ __device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restr
         __syncthreads();
         n = __builtin_amdgcn_readfirstlane(cnt[j & 1u]);
     }
-    // the last words are finished where they sit in the queue; when they
-    // fit one wave (all but the 16-block limit) that is wave parity % 4, so
-    // that over consecutive calls every wave takes a turn
-    const uint32_t lead = 0;
-    if (threadIdx.x - lead < n) {
+    // the last words are finished where they sit in the queue
+    if (threadIdx.x < n) {
         uint32_t owner;
-        WordState r = pop_word(Q, threadIdx.x - lead, owner);
-        class_masks<R>(r, thr, M, th);
-        compare_levels<R>(G, g, t, r.s, M, th, picks, q, 16, r.acc, r.und);
-        r.acc |= r.und;  // equal on all 32 bits: r == thr, accepted
-        if (r.acc) store64<kGlobal>(S, r.s, r.w ^ r.acc);
+        finish_word<R, kGlobal>(G, S, g, t, pop_word(Q, threadIdx.x, owner), q);
     }
 }
 
@@ -484,9 +469,7 @@ __device__ __forceinline__ void sweep_block(const GroupDev& G, uint64_t* __restr
                                             uint32_t q_split, SweepQueue& Q, uint32_t parity) {
     WordState st{};
     if (valid) st = load_word<kGlobal>(G, S, colour, idx);
-    Picks picks;
-    if (R < 3) picks.load(G.thr + g * kThrStride);
-    sweep_words<R, kGlobal>(G, S, g, t, st, valid, q_split, picks, Q, parity);
+    sweep_words<R, kGlobal>(G, S, g, t, st, valid, q_split, Q, parity);
 }
 
 // Column walk: thread `item` of a slot owns column (x, y) = item mod L^2 of
@@ -551,8 +534,6 @@ __device__ __forceinline__ void walk_block(const GroupDev& G, uint64_t* __restri
         }
     }
     const uint32_t site0 = plane0 + row + x;
-    Picks picks;
-    picks.load(G.thr + g * kThrStride);
     const uint64_t* S0 = scalar_ptr(S);
     const uint64_t* Jx = scalar_ptr(G.Jx);
     const uint64_t* Jy = scalar_ptr(G.Jy);
@@ -592,7 +573,7 @@ __device__ __forceinline__ void walk_block(const GroupDev& G, uint64_t* __restri
             st.nt2 = bop3<kNeNe>(w, above, below);
             below = above;
         }
-        sweep_words<R, true>(G, S, g, t, st, valid, G.q_split, picks, Q, k);
+        sweep_words<R, true>(G, S, g, t, st, valid, G.q_split, Q, k);
     }
 }
 // S: the slot's spins (global memory, or a copy in LDS).
@@ -790,8 +771,9 @@ k_chunk_fused(const BatchPlan slots, const uint32_t* __restrict__ ctr, uint32_t 
 // (order-independent, exact).
 // ---------------------------------------------------------------------------
 // Bit-sliced per-lane counter: value = ones + 2 twos + 4 fours + 8 * (hi as
-// a binary number).  Planes are added eight at a time with carry-save adders
-// (Harley-Seal), so each added plane costs about two bitop3 per 32 lanes.
+// a binary number).  Planes are added four at a time with carry-save adders
+// (Harley-Seal): three adders, then the carry into `fours` and the binary
+// part rippled once per four planes.
 // Binary planes a LaneCounter needs above ones/twos/fours to hold `max`.
 constexpr int counter_planes(int max) {
     int nh = 0;
@@ -816,17 +798,15 @@ __device__ __forceinline__ void csa(uint64_t& h, uint64_t& l, uint64_t a, uint64
 }
 
 template <int NH>
-__device__ __forceinline__ void add8(LaneCounter<NH>& c, const uint64_t (&x)[8]) {
-    uint64_t twosA, twosB, foursA, foursB, eights;
+__device__ __forceinline__ void add4(LaneCounter<NH>& c, const uint64_t (&x)[4]) {
+    uint64_t twosA, twosB, fours;
     csa(twosA, c.ones, c.ones, x[0], x[1]);
     csa(twosB, c.ones, c.ones, x[2], x[3]);
-    csa(foursA, c.twos, c.twos, twosA, twosB);
-    csa(twosA, c.ones, c.ones, x[4], x[5]);
-    csa(twosB, c.ones, c.ones, x[6], x[7]);
-    csa(foursB, c.twos, c.twos, twosA, twosB);
-    csa(eights, c.fours, c.fours, foursA, foursB);
+    csa(fours, c.twos, c.twos, twosA, twosB);
+    uint64_t eights = c.fours & fours;
+    c.fours ^= fours;
 #pragma unroll
-    for (int i = 0; i < NH; ++i) {  // ripple the eights into the binary part
+    for (int i = 0; i < NH; ++i) {
         const uint64_t carry = c.hi[i] & eights;
         c.hi[i] ^= eights;
         eights = carry;
@@ -834,23 +814,37 @@ __device__ __forceinline__ void add8(LaneCounter<NH>& c, const uint64_t (&x)[8])
 }
 
 // 64 x 64 bit transpose across the wave: afterwards thread t holds, in bit
-// b, bit t of thread b's word.  Stage s exchanges with thread t ^ s the bits
-// whose index differs from t in bit s (swapping bit s of the thread index
-// with bit s of the bit index); the six stages commute.
+// b, bit t of thread b's word.  Stage k exchanges with thread t ^ 2^k the
+// bits whose index differs from t in bit k (swapping bit k of the thread
+// index with bit k of the bit index); the six stages commute.  Stage 5
+// swaps the roles of the two 32-bit halves: a thread sends its partner the
+// half the partner keeps and takes one half back.  Stages 0-4 stay inside
+// each half: a thread keeps its bits on one side of bit k (mask K) and takes
+// the partner's other side, rotated into place by one v_alignbit (right by
+// 2^k if it keeps the upper side, else by 32 - 2^k), then one v_bitop3
+// merges the two.
 __device__ __forceinline__ uint64_t wave_transpose(uint64_t x) {
     const uint32_t t = threadIdx.x & 63u;
-    constexpr uint64_t kHigh[6] = {0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull,
-                                   0xF0F0F0F0F0F0F0F0ull, 0xFF00FF00FF00FF00ull,
-                                   0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
-#pragma unroll
-    for (int k = 5; k >= 0; --k) {
-        const uint32_t sh = 1u << k;
-        const uint64_t m = kHigh[k];  // bits b with b & sh set
-        const uint64_t y = lo_hi((uint32_t)__shfl_xor((int)(uint32_t)x, (int)sh, 64),
-                                 (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), (int)sh, 64));
-        x = (t & sh) ? ((x & m) | ((y & m) >> sh)) : ((x & ~m) | ((y & ~m) << sh));
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {
+        const bool up = (t & 32u) != 0;
+        const uint32_t recv = (uint32_t)__shfl_xor((int)(up ? lo : hi), 32, 64);
+        lo = up ? recv : lo;
+        hi = up ? hi : recv;
     }
-    return x;
+    constexpr uint32_t kHigh[5] = {0xAAAAAAAAu, 0xCCCCCCCCu, 0xF0F0F0F0u, 0xFF00FF00u, 0xFFFF0000u};
+#pragma unroll
+    for (int k = 4; k >= 0; --k) {
+        const uint32_t sh = 1u << k;
+        const bool up = (t & sh) != 0;
+        const uint32_t keep = up ? kHigh[k] : ~kHigh[k];
+        const uint32_t rot = up ? sh : 32u - sh;
+        const uint32_t ylo = (uint32_t)__shfl_xor((int)lo, (int)sh, 64);
+        const uint32_t yhi = (uint32_t)__shfl_xor((int)hi, (int)sh, 64);
+        lo = BITOP3(keep, lo, __builtin_amdgcn_alignbit(ylo, ylo, rot), kSelect);
+        hi = BITOP3(keep, hi, __builtin_amdgcn_alignbit(yhi, yhi, rot), kSelect);
+    }
+    return lo_hi(lo, hi);
 }
 
 // Per-lane totals over the wave's 64 threads of a bit-sliced counter: thread
@@ -870,19 +864,36 @@ __device__ __forceinline__ uint32_t lane_total(const LaneCounter<NH>& c) {
 // bottom to top.  Each bond is counted once, from its lower endpoint: per
 // word the +x and +y neighbours in the same plane and the word above, which
 // is the next step's centre, so a step costs three loads; the offsets are
-// fixed for the walk and the slot base advances one plane per step.  Eight
-// steps are loaded before their planes enter the counters.  Only the tile's
-// last bond can wrap round tau.
+// fixed for the walk and the slot base advances one plane per step.  Only
+// the tile's last bond can wrap round tau.
+//
+// The walk runs in batches of kEnergyBatch steps, software-pipelined: the
+// loads of the next batch are issued before the current batch is counted,
+// so every wave keeps loads in flight while it adds.  For that the loads of
+// a batch take no branch (the compiler would otherwise wait for every load
+// in flight before counting): steps past the tile's end re-read its last
+// plane and are not counted, the wrapping bond's word comes through a
+// selected offset, and its antiperiodic sign is applied when counting.
+constexpr int kEnergyBatch = 4;
+
+struct EnergyBatch {
+    uint64_t up[kEnergyBatch], xp[kEnergyBatch], yp[kEnergyBatch];
+};
+
 template <int kMaxPlanes>
 __device__ __forceinline__ void energy_walk(const GroupDev& G, uint32_t g, uint32_t item,
                                             uint32_t planes, int32_t* __restrict__ cnt) {
     const uint32_t L = G.L, P = L * L;
+    const uint32_t n_items = G.V >> __builtin_ctz(planes);
+    // a wave without a column (the tail of a slot's last block) has nothing
+    // to add: it leaves before the cross-lane transposes
+    if (__builtin_amdgcn_readfirstlane(item) >= n_items) return;
     const uint64_t* __restrict__ S = G.spins + (size_t)g * G.V;
     // per thread and lane at most 2*kMaxPlanes unsatisfied space bonds and
     // kMaxPlanes time bonds or differing pairs
     LaneCounter<counter_planes(2 * kMaxPlanes)> Csp;
     LaneCounter<counter_planes(kMaxPlanes)> Ct, Cq;
-    if (item < (G.V >> __builtin_ctz(planes))) {
+    if (item < n_items) {
         const uint32_t tile = fast_div(item, G.div_plane);
         const uint32_t col = item - tile * P;
         const uint32_t y = fast_div(col, G.div_row);
@@ -890,31 +901,38 @@ __device__ __forceinline__ void energy_walk(const GroupDev& G, uint32_t g, uint3
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
         const uint32_t yp = (y + 1 == L) ? 0 : y + 1;
         const uint32_t base = tile * planes * P;
-        uint32_t o_c = (base + col) * 8u, o_up = o_c + P * 8u;
+        // byte offsets: o_xp, o_yp from the step's plane; up words from S
         uint32_t o_xp = (base + y * L + xp) * 8u, o_yp = (base + yp * L + x) * 8u;
+        uint32_t o_up = (base + col + P) * 8u;
+        const uint32_t o_wrap = col * 8u;  // slice 0, above the top slice
         const uint64_t jx = G.Jx[col], jy = G.Jy[col];
         const bool top = tile * planes + planes == G.Ltau;  // the last bond wraps to slice 0
-        uint64_t w = load_at(S, o_c);
-#pragma unroll 1
-        for (uint32_t k0 = 0; k0 < planes; k0 += 8) {
+        const uint64_t flip = (top && G.anti) ? ~0ull : 0ull;  // antiperiodic wrap bond
+        const uint32_t last = planes - 1;
+        auto fetch = [&](uint32_t k0, EnergyBatch& B) {
             asm volatile("" : "+v"(o_up), "+v"(o_xp), "+v"(o_yp));  // 32-bit offsets in the loop
-            uint64_t xs[8], ys[8], ts[8], qs[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < kEnergyBatch; ++k) {
+                const uint32_t kk = min(k0 + k, last);  // block-uniform
+                const uint64_t* Sk = scalar_ptr(S + (size_t)kk * P);
+                B.xp[k] = load_at(Sk, o_xp);
+                B.yp[k] = load_at(Sk, o_yp);
+                B.up[k] = load_at(S, (top && kk == last) ? o_wrap : o_up + kk * P * 8u);
+            }
+        };
+        uint64_t w = load_at(S, (base + col) * 8u);
+        // kGuard: some steps of the batch may lie past the tile's end
+        auto count = [&](auto guard, uint32_t k0, const EnergyBatch& B) {
+            constexpr bool kGuard = decltype(guard)::value;
+            uint64_t xs[kEnergyBatch], ys[kEnergyBatch], ts[kEnergyBatch], qs[kEnergyBatch];
+#pragma unroll
+            for (int k = 0; k < kEnergyBatch; ++k) {
                 xs[k] = ys[k] = ts[k] = qs[k] = 0;
-                if (k0 + k < planes) {  // block-uniform
-                    const uint64_t* Sk = scalar_ptr(S + (size_t)(k0 + k) * P);
-                    const uint64_t nxp = load_at(Sk, o_xp), nyp = load_at(Sk, o_yp);
-                    uint64_t up;
-                    if (top && k0 + k + 1 == planes) {
-                        up = load64<true>(S, col);
-                        if (G.anti) up = ~up;  // antiperiodic wrap bond
-                    } else {
-                        up = load_at(Sk, o_up);
-                    }
-                    xs[k] = bop3<kXor3>(w, nxp, jx);  // +x bond unsatisfied
-                    ys[k] = bop3<kXor3>(w, nyp, jy);  // +y bond unsatisfied
-                    ts[k] = w ^ up;                   // +tau bond unsatisfied
+                if (!kGuard || k0 + k < planes) {  // block-uniform
+                    const uint64_t up = B.up[k];
+                    xs[k] = bop3<kXor3>(w, B.xp[k], jx);  // +x bond unsatisfied
+                    ys[k] = bop3<kXor3>(w, B.yp[k], jy);  // +y bond unsatisfied
+                    ts[k] = bop3<kXor3>(w, up, k0 + k == last ? flip : 0ull);  // +tau bond
                     // pair (2p, 2p+1) differs; pairs never straddle the halves
                     const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
                     qs[k] = lo_hi(BITOP3(lo, lo >> 1, 0x55555555u, 0x28),
@@ -922,10 +940,29 @@ __device__ __forceinline__ void energy_walk(const GroupDev& G, uint32_t g, uint3
                     w = up;
                 }
             }
-            add8(Csp, xs);
-            add8(Csp, ys);
-            add8(Ct, ts);
-            add8(Cq, qs);
+            add4(Csp, xs);
+            add4(Csp, ys);
+            add4(Ct, ts);
+            add4(Cq, qs);
+        };
+        EnergyBatch b0, b1;
+        if (planes % (2 * kEnergyBatch) == 0) {
+            // two batch buffers used in turn (no copies between them); the
+            // last fetch re-reads the top plane and is not counted
+            fetch(0, b0);
+#pragma unroll 1
+            for (uint32_t k0 = 0; k0 < planes; k0 += 2 * kEnergyBatch) {
+                fetch(k0 + kEnergyBatch, b1);
+                count(std::false_type{}, k0, b0);
+                fetch(k0 + 2 * kEnergyBatch, b0);
+                count(std::false_type{}, k0 + kEnergyBatch, b1);
+            }
+        } else {  // tiles of 2 or 4 planes
+#pragma unroll 1
+            for (uint32_t k0 = 0; k0 < planes; k0 += kEnergyBatch) {
+                fetch(k0, b0);
+                count(std::true_type{}, k0, b0);
+            }
         }
     }
     // every thread of the wave takes part in the transposes
@@ -950,7 +987,8 @@ k_energy_batched(const BatchPlan plan) {
     const GroupDev G = group_record<false>(plan, at.gi);
     const uint32_t local = at.local;
     const uint32_t nb = energy_blocks_per_slot(G.V, G.etile);
-    const uint32_t g = local / nb;
+    // block-uniform: keeps the slot's address arithmetic on the scalar unit
+    const uint32_t g = __builtin_amdgcn_readfirstlane(local / nb);
     energy_walk<kEnergyWords>(G, g, (local - g * nb) * kEnergyBlock + threadIdx.x, G.etile, G.cnt);
 }
 
