@@ -143,6 +143,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default colour-pass schedule instead of tuning it per shape")
+    ap.add_argument("--schedules", metavar="JSON",
+                    help="take the colour-pass schedules from this file (written by "
+                         "--save-schedules) instead of tuning them")
+    ap.add_argument("--save-schedules", metavar="JSON",
+                    help="write the schedules used to this file (for profiling runs)")
     ap.add_argument("--cpu-sweeps", type=int, default=0,
                     help="oracle sweeps for the CPU baseline (0: about 15 s of work)")
     ap.add_argument("--overlaps", action="store_true",
@@ -200,9 +205,13 @@ def main():
     words_per_sweep = sum(g.words for g in wl.groups)
 
     schedules = {}
-    if not args.no_autotune:
+    if args.schedules:
+        schedules = autotune.load_cache(args.schedules)
+    elif not args.no_autotune:
         print("[bench] tuning the colour-pass schedule per shape", file=sys.stderr, flush=True)
         schedules = autotune.tune(wl.groups, log=lambda m: print(m, file=sys.stderr, flush=True))
+    if args.save_schedules:
+        autotune.save_cache(schedules, args.save_schedules)
     ens = qsg.Ensemble(wl.groups, pt_every=pe, swaplog_cap=64)
     if schedules:
         autotune.apply(ens, schedules)
@@ -236,9 +245,15 @@ def main():
     sec_other = timed(lambda: ens.sweep(pe * args.plain_steps, forms[other]))
     ps_other = sec_other / (pe * args.plain_steps * upd_per_sweep) * 1e12
 
-    print(f"[bench] timing {args.plain_steps} plain steps", file=sys.stderr, flush=True)
+    # per-sample launches: their own walk depth (they fill the chip one group
+    # at a time), then back to the batched schedules
+    plain_tile, _ = autotune.pick_plain_tile(ens, schedules)
+    print(f"[bench] timing {args.plain_steps} plain steps (walk depth {plain_tile})",
+          file=sys.stderr, flush=True)
     sec_plain = timed(lambda: ens.sweep(pe * args.plain_steps, qsg.QSG_PLAIN))
     ps_plain = sec_plain / (pe * args.plain_steps * upd_per_sweep) * 1e12
+    for i, g in enumerate(ens.groups):
+        ens.set_schedule(i, *schedules.get(autotune.shape_key(g), autotune.DEFAULT))
 
     # dominant kernel: the batched colour pass; average launch duration from
     # events around sweeps without PT (two pass launches + one tiny counter
@@ -279,6 +294,7 @@ def main():
         },
         f"{other}_ps_per_spin_update": round(ps_other, 5),
         "plain_ps_per_spin_update": round(ps_plain, 5),
+        "plain_tau_tile": plain_tile,
         "batched_speedup_vs_plain": round(ps_plain / ps_batched, 4),
         "spin_updates_per_s": upd_per_sweep * pe * args.steps / sec,
         "wall_s_timed_region": round(wall, 4),

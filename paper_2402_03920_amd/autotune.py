@@ -14,16 +14,20 @@ that every candidate gives the same trajectory):
   large values leave more waves running the long tail of levels; the best
   value depends on the class mix, hence on beta and the ladder.
 
-Groups are tuned by class: (L, L_tau, beta, ladder kind and end points);
-the number of ladder points only scales the work.  The best walk depth
-depends on how full the chip is, so a class is timed at the size of the
-whole ensemble, up to SCALE_WORDS: its groups are repeated until the timed
-sub-ensemble holds that many words (a class timed on its own would favour
-shallow walks that lose once the other classes share the chip; beyond
-2^26 words every candidate fills the chip several times over).  Per class
-the tuner first times every walk depth at the default split, then every
-split at the best depth (HIP events on the library's stream, the median of
-`repeats` runs of `sweeps` sweeps).  A candidate replaces the default only
+The walk depth is chosen for the whole ensemble: the batched launch deals
+its blocks to the eight XCDs in equal contiguous runs, so blocks of unequal
+depth (unequal work) leave some XCDs idle at the end of the pass; a mix of
+per-class depths measured 13 % slower than one depth for all.  The tuner
+times the whole ensemble under every depth (the library takes, per group,
+the largest power of two not above the request that divides L_tau).  The
+split is chosen per class (L, L_tau, beta, ladder kind and end points; the
+number of ladder points only scales the work), at that depth.  Both are
+timed at the size of the whole ensemble, up to SCALE_WORDS: the groups are
+repeated until the timed ensemble holds that many words (a class timed on
+its own would favour shallow walks that lose once the other classes share
+the chip; beyond 2^26 words every candidate fills the chip several times
+over).  Each timing is the median of `repeats` runs of `sweeps` sweeps (HIP
+events on the library's stream); a candidate replaces the default only
 when it is faster by more than `tie`, which keeps picks stable from run to
 run.
 
@@ -50,16 +54,6 @@ def shape_key(g) -> str:
         return f"L{g.L}_Lt{g.L_tau}_K{float(g.gammas[0]):.6g}-{float(g.gammas[-1]):.6g}"
     return (f"L{g.L}_Lt{g.L_tau}_b{float(g.beta):.6g}_"
             f"G{float(g.gammas[0]):.6g}-{float(g.gammas[-1]):.6g}")
-
-
-def valid_tiles(L_tau: int, tiles: Iterable[int] = TILES) -> List[int]:
-    """Walk depths that are a distinct power of two dividing L_tau (the
-    library takes the largest power of two <= the request dividing L_tau)."""
-    return [t for t in tiles if L_tau % t == 0]
-
-
-def default_for(L_tau: int) -> Tuple[int, int]:
-    return DEFAULT[0], max(t for t in valid_tiles(L_tau) if t <= DEFAULT[1])
 
 
 def group_words(g) -> int:
@@ -135,38 +129,46 @@ def tune(groups, splits: Iterable[int] = SPLITS, tiles: Iterable[int] = TILES,
          cache: Dict[str, Tuple[int, int]] | None = None, tie: float = 0.01,
          scale_words: int | None = None, log=None, report: Dict | None = None
          ) -> Dict[str, Tuple[int, int]]:
-    """Best (sweep_split, tau_tile) for every class present in `groups`,
-    each class timed at `scale_words` words (default: the whole ensemble's,
-    at most SCALE_WORDS).
-    `report`, if given, receives per class the timings of every candidate."""
+    """(sweep_split, tau_tile) for every class present in `groups`: one walk
+    depth for the ensemble, a split per class, timed at `scale_words` words
+    (default: the whole ensemble's, at most SCALE_WORDS).  Classes already
+    in `cache` keep their entry; the others get the depth tuned now.
+    `report`, if given, receives the timings: report["tiles"] per depth and
+    report[class] = {"splits": ..., "pick": ...}."""
     cache = {} if cache is None else cache
     by_class: Dict[str, List] = {}
     for g in groups:
         by_class.setdefault(shape_key(g), []).append(g)
+    todo = [k for k in by_class if k not in cache]
+    if not todo:
+        return cache
     words = min(sum(group_words(g) for g in groups), SCALE_WORDS) if scale_words is None \
         else scale_words
-    for key, gs in by_class.items():
-        if key in cache:
-            continue
-        L_tau = gs[0].L_tau
-        default = default_for(L_tau)
+    split0, tile0 = DEFAULT
+    with qsg.Ensemble(at_scale(list(groups), words), pt_every=0, swaplog_cap=1) as ens:
+        ens.init_spins()
+        ens.sweep(2, qsg.QSG_BATCHED | qsg.QSG_NO_PT)
+        t_tiles = time_candidates(ens, [(split0, t) for t in sorted(set(tiles) | {tile0})])
+    tile = _pick(t_tiles, (split0, tile0), tie)[1]
+    if report is not None:
+        report["tiles"] = {c[1]: t for c, t in t_tiles.items()}
+    if log:
+        log(f"[autotune] walk depth at {words} words: "
+            + ", ".join(f"{c[1]}:{t * 1e6:.1f}us" for c, t in sorted(t_tiles.items()))
+            + f" -> tile {tile}")
+    for key in todo:
+        gs = by_class[key]
         with qsg.Ensemble(at_scale(gs, words), pt_every=0, swaplog_cap=1) as ens:
             ens.init_spins()
             ens.sweep(2, qsg.QSG_BATCHED | qsg.QSG_NO_PT)
-            tile_cands = sorted(set(valid_tiles(L_tau, tiles)) | {default[1]})
-            t_tiles = time_candidates(ens, [(default[0], t) for t in tile_cands])
-            tile = _pick(t_tiles, default, tie)[1]
-            base = (default[0], tile)
-            t_splits = time_candidates(ens, [(s, tile) for s in splits if s != base[0]])
-            t_splits[base] = t_tiles[base]
-            best = _pick(t_splits, base, tie)
+            t_splits = time_candidates(ens, [(s, tile) for s in sorted(set(splits) | {split0})])
+        best = _pick(t_splits, (split0, tile), tie)
         cache[key] = best
         if report is not None:
-            report[key] = {"tiles": t_tiles, "splits": t_splits, "pick": best}
+            report[key] = {"splits": t_splits, "pick": best}
         if log:
             log(f"[autotune] {key} at {words} words: "
-                + ", ".join(f"{c[0]}/{c[1]}:{t * 1e6:.1f}us"
-                            for c, t in sorted({**t_tiles, **t_splits}.items()))
+                + ", ".join(f"{c[0]}:{t * 1e6:.1f}us" for c, t in sorted(t_splits.items()))
                 + f" -> split {best[0]}, tile {best[1]}")
     return cache
 
@@ -181,6 +183,27 @@ def apply(ens, cache: Dict[str, Tuple[int, int]]) -> int:
             ens.set_schedule(i, split, tile)
             n += 1
     return n
+
+
+def pick_plain_tile(ens, cache: Dict[str, Tuple[int, int]], tiles: Iterable[int] = TILES,
+                    sweeps: int = 2, repeats: int = 3):
+    """Walk depth for per-sample launches (QSG_PLAIN), which fill the chip
+    one group at a time and so want shallower walks than the batched pass:
+    every depth is timed over the whole ensemble (each group keeps its
+    cached split).  Leaves the ensemble on the best depth; returns it and
+    the seconds per sweep of every depth."""
+    timed = _timer(ens.stream)
+    times = {}
+    for tile in sorted(set(tiles)):
+        for i, g in enumerate(ens.groups):
+            ens.set_schedule(i, cache.get(shape_key(g), DEFAULT)[0], tile)
+        ens.sweep(1, qsg.QSG_PLAIN | qsg.QSG_NO_PT)
+        times[tile] = _median([timed(lambda: ens.sweep(sweeps, qsg.QSG_PLAIN | qsg.QSG_NO_PT))
+                               / sweeps for _ in range(repeats)])
+    best = min(times, key=times.get)
+    for i, g in enumerate(ens.groups):
+        ens.set_schedule(i, cache.get(shape_key(g), DEFAULT)[0], best)
+    return best, times
 
 
 FORMS = {"per-pass": qsg.QSG_BATCHED | qsg.QSG_GRAPH,
