@@ -155,6 +155,9 @@ def parse():
     ap.add_argument("--transfer", action="store_true",
                     help="time the transfer-matrix product (L = 5 sector) and a Lanczos solve "
                          "instead (one JSON line)")
+    ap.add_argument("--mlp", action="store_true",
+                    help="time the ladder network's kernels (forward, training step) instead "
+                         "(one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     return ap.parse_args()
@@ -189,6 +192,9 @@ def main():
         return
     if args.transfer:
         transfer_bench(args)
+        return
+    if args.mlp:
+        mlp_bench(args)
         return
     import numpy as np
     import torch
@@ -384,6 +390,60 @@ def overlap_bench(args):
                                    "unit": "T VALU lane-instructions/s",
                                    "frac": round(model / sec / 1e12 / PEAK_VALU_TOPS, 4)},
                       "note": "HIP events around one launch over all slots on the library's stream"}),
+          flush=True)
+
+
+def mlp_bench(args):
+    """Time the ladder network's kernels (6 -> 128 -> 128 -> 128 -> 32, one
+    thread per output, FP32 accumulation) at batch sizes from one sample to
+    the allocation-free limit: the forward pass with FP32 and with BF16
+    operands, and one training step (forward, loss, backward, Adam), with
+    HIP events around back-to-back calls on one stream.  Work per sample:
+    2 x (6*128 + 2*128*128 + 128*32) = 75 264 flops forward."""
+    import numpy as np
+    import torch
+    from paper_2402_03920_amd import ladder, qsg
+    torch.cuda.set_device(0)
+    flops_fwd = 2 * (6 * 128 + 2 * 128 * 128 + 128 * 32)
+    reps = max(args.steps, 20)
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        for _ in range(reps):
+            fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3 / reps
+
+    rows = []
+    rng = np.random.default_rng(11)
+    for B in (1, 32, 128, 1024):
+        x = torch.tensor(rng.normal(size=(B, 6)).astype(np.float32), device="cuda")
+        t_inc = torch.full((B, 31), 1.0 / 31, dtype=torch.float32, device="cuda")
+        t_log = torch.zeros(B, dtype=torch.float32, device="cuda")
+        row = {"batch": B}
+        for name, bf16 in (("fp32", False), ("bf16", True)):
+            net = ladder.LadderMLP(seed=3, bf16=bf16)
+            ws = torch.empty(int(qsg.lib().qsg_mlp_workspace_floats(B)), dtype=torch.float32,
+                             device="cuda")
+            out = torch.empty((B, 32), dtype=torch.float32, device="cuda")
+            sec = timed(lambda: qsg.qsg_mlp_forward(net.params, net.bf16, x, out, ws))
+            row[f"forward_{name}_us"] = round(sec * 1e6, 2)
+            row[f"forward_{name}_gflops"] = round(flops_fwd * B / sec / 1e9, 2)
+        net = ladder.LadderMLP(seed=3, bf16=True)
+        sec = timed(lambda: net.train_step(x, t_inc, t_log, 1e-4))
+        row["train_step_us"] = round(sec * 1e6, 2)
+        rows.append(row)
+    print(json.dumps({"metric": "ladder network kernels", "unit": "us per call",
+                      "higher_is_better": False, "reps": reps, "rows": rows,
+                      "note": "one thread per output, FP32 accumulation; latency-bound at "
+                              "these sizes (a training step is a handful of launches)"}),
           flush=True)
 
 
