@@ -382,16 +382,8 @@ __device__ __forceinline__ WordState pop_word(const SweepQueue& Q, uint32_t k, u
     return r;
 }
 
-// The colour-pass update of one word per thread of the block: the first
-// q_split Philox blocks of levels for every word; then, while the words with
-// undecided lanes fill more than one wave, they are packed into the first
-// waves of the block and given one more block; the last ones (at most one
-// wave) are finished there.  Far fewer waves run the long tail of levels.
-// Every thread of the block calls this (it synchronises); `valid` is false
-// for threads without a word (st is then unused).  Packing counters: one
-// pair per call parity (see SweepQueue); within a call, round j writes
-// counter j & 1, which round j - 1 cleared after every thread had read its
-// previous value.
+// The comparison of one word from level block q to the end (16 blocks, all
+// 32 bits), then its update.
 template <int R, bool kGlobal>
 __device__ __forceinline__ void finish_word(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
                                             uint32_t t, WordState r, uint32_t q) {
@@ -405,6 +397,16 @@ __device__ __forceinline__ void finish_word(const GroupDev& G, uint64_t* __restr
     if (r.acc) store64<kGlobal>(S, r.s, r.w ^ r.acc);
 }
 
+// The colour-pass update of one word per thread of the block: the first
+// q_split Philox blocks of levels for every word; then, while the words with
+// undecided lanes fill more than one wave, they are packed into the first
+// waves of the block and given one more block; the last ones (at most one
+// wave) are finished there.  Far fewer waves run the long tail of levels.
+// Every thread of the block calls this (it synchronises); `valid` is false
+// for threads without a word (st is then unused).  Packing counters: one
+// pair per call parity (see SweepQueue); within a call, round j writes
+// counter j & 1, which round j - 1 cleared after every thread had read its
+// previous value.
 template <int R, bool kGlobal>
 __device__ __forceinline__ void sweep_words(const GroupDev& G, uint64_t* __restrict__ S, uint32_t g,
                                             uint32_t t, WordState st, bool valid, uint32_t q_split,
