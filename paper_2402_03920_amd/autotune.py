@@ -17,7 +17,7 @@ that every candidate gives the same trajectory):
 The walk depth is chosen for the whole ensemble: the batched launch deals
 its blocks to the eight XCDs in equal contiguous runs, so blocks of unequal
 depth (unequal work) leave some XCDs idle at the end of the pass; a mix of
-per-class depths measured 13 % slower than one depth for all.  The tuner
+per-class depths measured 12 % slower than one depth for all.  The tuner
 times the whole ensemble under every depth (the library takes, per group,
 the largest power of two not above the request that divides L_tau).  The
 split is chosen per class (L, L_tau, beta, ladder kind and end points; the
@@ -33,6 +33,8 @@ run.
 
 `pick_form` makes the other, ensemble-wide choice: whether a PT chunk runs
 as one launch per colour pass or as one fused launch for all its sweeps.
+`pick_plain_tile` chooses the depth of per-sample launches, which fill the
+chip one group at a time.
 """
 from __future__ import annotations
 
