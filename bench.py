@@ -8,11 +8,17 @@ chunk over every sample: 10 sweeps (red + blue pass each), the
 energy/overlap pass, the PT step and the exchange pass.
 
 Prints one JSON line.  value = picoseconds per spin-update of the batched
-path (one launch per pass over all samples, replayed as a HIP graph);
-plain_ps_per_spin_update is the same work launched per sample.  The other
+path (one launch per pass over all samples, replayed as a HIP graph, the
+faster of the per-pass and fused forms; colour-pass schedules tuned first:
+one walk depth for the ensemble, a split per shape class);
+plain_ps_per_spin_update is the same work launched per sample, at the walk
+depth best for per-sample launches.  The other
 half of the metric, PT round trips per hour with the learned against the
 geometric ladder, is measured by `python -m paper_2402_03920_amd.learn_ladder`
 (profiles/ladder_eval_results.txt); the line quotes that record.
+Other modes print their own line: --overlaps (Euclidean-time overlaps),
+--transfer (transfer-matrix product and Lanczos), --mlp (ladder network
+kernels), --copy-calibration (a plain copy for scaling HBM counters).
 """
 from __future__ import annotations
 
