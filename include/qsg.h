@@ -352,6 +352,19 @@ qsg_status qsg_tau_overlaps(qsg_ctx* ctx, uint32_t group, uint32_t first_slot, u
                             const uint32_t* taus, uint32_t n_taus, int64_t* d_out,
                             size_t out_words);
 
+/* The observables of App. E (`overlap_tau`: Q2, Q4 and F as functions of
+ * the Euclidean-time distance) from the integer sums of qsg_tau_overlaps
+ * over n_configs configurations of one slot: host arrays q2 [64][n_taus],
+ * q4 [64][n_taus], A [n_taus][L], B [n_taus][L] (one slot's block of the
+ * overlaps output, summed), averaged over tau1, the configurations and the
+ * 64 replicas: Q2[i] = mean_lanes q2 / (L_tau n_configs), likewise Q4, and
+ * F[i] = sum_d (A+B)[i][d] cos(2 pi d / L) / (2 * 64 * L_tau * n_configs).
+ * Outputs are host arrays of n_taus doubles.  Host only: no device, no
+ * context.  QSG_E_INVALID for null pointers, L = 0, L_tau = 0, n_taus = 0
+ * or n_configs = 0. */
+qsg_status qsg_tau_observables(const int64_t* sums, uint32_t L, uint32_t L_tau, uint32_t n_taus,
+                               uint64_t n_configs, double* Q2, double* Q4, double* F);
+
 /* Random-number ceiling of the device (measurement only; the generator of
  * Sec. 2.1.1): thread i < n_threads generates `blocks` Philox4x32-10 blocks
  * with counters (i, 0, b, 0), b < blocks, under key (key lo, key hi) -- the

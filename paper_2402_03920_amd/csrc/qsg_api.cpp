@@ -10,6 +10,7 @@
 
 #include <chrono>
 #include <cstdarg>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -1045,6 +1046,32 @@ qsg_status qsg_tau_overlaps(qsg_ctx* c, uint32_t group, uint32_t first_slot, uin
     if (out_words < need) return fail(c, QSG_E_BUFFER, "output needs %zu int64", need);
     QSG_HIP(c, qsg::launch_tau_overlaps(g.spins + (size_t)first_slot * g.V, n_slots, g.L, g.Ltau,
                                         tl, d_out, c->stream));
+    return QSG_OK;
+}
+
+qsg_status qsg_tau_observables(const int64_t* sums, uint32_t L, uint32_t L_tau, uint32_t n_taus,
+                               uint64_t n_configs, double* Q2, double* Q4, double* F) {
+    if (!sums || !Q2 || !Q4 || !F) return fail(nullptr, QSG_E_INVALID, "null buffer");
+    if (L == 0 || L_tau == 0 || n_taus == 0 || n_configs == 0)
+        return fail(nullptr, QSG_E_INVALID, "L, L_tau, n_taus and n_configs must be > 0");
+    const int64_t* q2 = sums;
+    const int64_t* q4 = q2 + (size_t)64 * n_taus;
+    const int64_t* A = q4 + (size_t)64 * n_taus;
+    const int64_t* B = A + (size_t)n_taus * L;
+    const double norm = (double)L_tau * (double)n_configs;
+    const double pi = 3.14159265358979323846;
+    for (uint32_t i = 0; i < n_taus; ++i) {
+        double s2 = 0.0, s4 = 0.0, f = 0.0;
+        for (uint32_t a = 0; a < 64; ++a) {  // lane order, as the average is defined
+            s2 += (double)q2[(size_t)a * n_taus + i];
+            s4 += (double)q4[(size_t)a * n_taus + i];
+        }
+        for (uint32_t d = 0; d < L; ++d)
+            f += (double)(A[(size_t)i * L + d] + B[(size_t)i * L + d]) * std::cos(2.0 * pi * d / L);
+        Q2[i] = s2 / 64.0 / norm;
+        Q4[i] = s4 / 64.0 / norm;
+        F[i] = f / (2.0 * norm * 64.0);
+    }
     return QSG_OK;
 }
 

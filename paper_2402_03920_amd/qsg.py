@@ -113,6 +113,8 @@ _SIGS = {
     "qsg_philox_probe": (C.c_int32, [C.c_uint32, C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p]),
     "qsg_tau_overlaps": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p,
                                      C.c_uint32, C.c_void_p, C.c_size_t]),
+    "qsg_tau_observables": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
+                                        C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "qsg_tm_dim": (C.c_uint64, [C.c_uint32]),
     "qsg_tm_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "qsg_tm_lanczos_workspace_bytes": (C.c_size_t, [C.c_uint32, C.c_uint32]),
@@ -465,14 +467,18 @@ def philox_device(inputs: np.ndarray) -> np.ndarray:
 
 
 def tau_observables(acc: dict, L: int, L_tau: int, n_configs: int) -> dict:
-    """Q2(tau), Q4(tau), F(tau) (App. E normalisation: averages over tau1,
-    configurations and the 64 replicas) from summed tau_overlaps output."""
-    import math
-    norm = float(L_tau) * n_configs
-    w = np.array([math.cos(2 * math.pi * d / L) for d in range(L)])
-    return {"Q2": acc["q2"].astype(np.float64).mean(axis=0) / norm,
-            "Q4": acc["q4"].astype(np.float64).mean(axis=0) / norm,
-            "F": ((acc["A"] + acc["B"]).astype(np.float64) @ w) / (2.0 * norm * 64)}
+    """Q2(tau), Q4(tau), F(tau) (qsg_tau_observables: App. E normalisation,
+    averages over tau1, configurations and the 64 replicas) from summed
+    tau_overlaps output of one slot."""
+    n = acc["q2"].shape[1]
+    sums = np.ascontiguousarray(np.concatenate(
+        [np.asarray(acc[k], dtype=np.int64).ravel() for k in ("q2", "q4", "A", "B")]))
+    if sums.size != n * (128 + 2 * L):
+        raise ValueError("sums do not match L and the number of tau values")
+    out = {k: np.zeros(n, dtype=np.float64) for k in ("Q2", "Q4", "F")}
+    _check(lib().qsg_tau_observables(_ptr(sums), int(L), int(L_tau), n, int(n_configs),
+                                     _ptr(out["Q2"]), _ptr(out["Q4"]), _ptr(out["F"])))
+    return out
 
 
 def philox_probe(out, n_threads: int, blocks: int, key: int, stream) -> None:
