@@ -276,23 +276,21 @@ def test_slot_size_limit_is_enforced_without_touching_the_device():
 
 def test_tau_observables_follow_the_normalisation_without_the_device():
     """qsg_tau_observables (host code of the library): App. E's averages over
-    tau1, configurations and replicas of summed integer overlaps, checked
-    against the definition on random sums, and its argument checks."""
-    import math
+    tau1, configurations and replicas of summed integer overlaps, against
+    the oracle's observables on random sums, and its argument checks."""
     import numpy as np
+    from oracle import overlaps
     from paper_2402_03920_amd import qsg
     rng = np.random.default_rng(12)
     for L, L_tau, n, confs in ((4, 8, 3, 1), (6, 10, 5, 7), (32, 64, 2, 2)):
         acc = {"q2": rng.integers(0, 10 ** 9, (64, n)), "q4": rng.integers(0, 10 ** 15, (64, n)),
                "A": rng.integers(-10 ** 6, 10 ** 6, (n, L)),
                "B": rng.integers(-10 ** 6, 10 ** 6, (n, L))}
-        o = qsg.tau_observables(acc, L, L_tau, confs)
-        norm = L_tau * confs
-        cos = np.array([math.cos(2 * math.pi * d / L) for d in range(L)])
-        assert np.allclose(o["Q2"], acc["q2"].mean(axis=0) / norm, rtol=1e-13, atol=0)
-        assert np.allclose(o["Q4"], acc["q4"].mean(axis=0) / norm, rtol=1e-13, atol=0)
-        assert np.allclose(o["F"], (acc["A"] + acc["B"]) @ cos / (2 * 64 * norm),
-                           rtol=1e-12, atol=1e-9)
+        got = qsg.tau_observables(acc, L, L_tau, confs)
+        want = overlaps.observables(acc, L, L_tau, confs)
+        for key in ("Q2", "Q4"):
+            assert np.allclose(got[key], want[key], rtol=1e-13, atol=0), key
+        assert np.allclose(got["F"], want["F"], rtol=1e-12, atol=1e-9)
     f = qsg.lib().qsg_tau_observables
     buf = np.zeros(2 * 128 + 4 * 4, dtype=np.int64)
     out = np.zeros(2)
